@@ -1,0 +1,141 @@
+"""FP32 inner block CG with FP64 outer iterative refinement -- oracle.
+
+TEST INFRASTRUCTURE ONLY. Not in the paper: this is the mixed-precision form
+of Algorithm 1 (Section 3, M = I). Its iterates depend on FP32 rounding order
+and are "parity unpinned"; what is compared with the GPU is the final FP64
+accuracy (true residual and distance to the FP64 solution).
+
+Inner solve (one restart per outer step, X starts at 0):
+  matrix values, the sparse product and all n x k block vectors in FP32;
+  the block products accumulated in FP64 from the FP32 inputs; the Cholesky
+  and LU solves in FP64; lambda and beta rounded to FP32 before the updates;
+  stop when every column's recursive residual fell by ``inner_tol`` relative
+  to the inner initial residual, or after ``inner_maxit`` iterations.
+Outer loop:
+  R = B - A X in FP64; stop when max_j ||R_j|| / ||R0_j|| <= tol;
+  scale by the single scalar s = max_j ||R_j|| (a per-column scale is not an
+  element of every subalgebra); solve A D = R/s in FP32; X += s * D;
+  if an outer step does not halve the largest relative residual, finish with
+  the FP64 iteration from the current X (flagged in the result).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import EBREAKDOWN, EINVAL, NOT_CONVERGED, OK
+from .bcg import (Breakdown, decoupled_columns, normalize_p, solve as solve64, solve_beta,
+                  solve_lambda)
+
+
+def _block_product64(X32, Y32, variant, p):
+    X = X32.astype(np.float64)
+    Y = Y32.astype(np.float64)
+    from .bcg import block_product
+    return block_product(X, Y, variant, p)
+
+
+def _apply32(Y32, C64, p):
+    C = C64.astype(np.float32)
+    n, k = Y32.shape
+    q = k // p
+    if p == 1:
+        c = C[:, 0, 0]
+        return Y32 * (c if c.shape[0] == k else c[0])
+    out = np.empty_like(Y32)
+    for g in range(q):
+        Cg = C[g] if C.shape[0] == q else C[0]
+        out[:, g * p:(g + 1) * p] = Y32[:, g * p:(g + 1) * p] @ Cg
+    return out
+
+
+def _norms32(R32):
+    R = R32.astype(np.float64)
+    return np.sqrt(np.einsum("ij,ij->j", R, R))
+
+
+def inner_solve32(A32, R32, variant, p, inner_tol, inner_maxit):
+    """FP32 block CG from X = 0 on A D = R32; returns (D, iterations, status)."""
+    dec = decoupled_columns(variant, p)
+    R = R32.copy()
+    X = np.zeros_like(R32)
+    r0 = _norms32(R)
+    if np.any(r0 == 0.0) and not dec:
+        return X, 0, EINVAL
+    safe = np.where(r0 == 0.0, 1.0, r0)
+    P = R.copy()
+    for i in range(1, inner_maxit + 1):
+        Q = (A32 @ P).astype(np.float32)
+        alpha = _block_product64(P, Q, variant, p)
+        rho_old = _block_product64(P, R, variant, p)
+        try:
+            lam = solve_lambda(alpha, rho_old, dec)
+        except Breakdown:
+            return X, i - 1, EBREAKDOWN
+        X = X + _apply32(P, lam, p)
+        R = R - _apply32(Q, lam, p)
+        ratios = np.where(r0 == 0.0, 0.0, _norms32(R) / safe)
+        if np.max(ratios) <= inner_tol:
+            return X, i, OK
+        if not np.all(np.isfinite(ratios)):
+            return X, i, EBREAKDOWN
+        rho_new = _block_product64(R, R, variant, p)
+        try:
+            beta = solve_beta(rho_old, rho_new, dec)
+        except Breakdown:
+            return X, i, EBREAKDOWN
+        P = R + _apply32(P, beta, p)
+    return X, inner_maxit, NOT_CONVERGED
+
+
+def solve(A, B, variant="block", p=0, tol=1e-8, maxit=100, inner_tol=1e-4, inner_maxit=1000,
+          X0=None):
+    """Mixed-precision solve; returns (X, info) with FP64 X."""
+    B = np.asarray(B, dtype=np.float64)
+    n, k = B.shape
+    X = np.zeros_like(B) if X0 is None else np.array(X0, dtype=np.float64, copy=True)
+    info = {"status": OK, "iterations": 0, "outer_iterations": 0, "fp64_fallback": False}
+    try:
+        p = normalize_p(variant, p, k)
+    except ValueError:
+        info["status"] = EINVAL
+        return X, info
+    A32 = A.astype(np.float32)
+    R = B - A @ X
+    r0 = np.sqrt(np.einsum("ij,ij->j", R, R))
+    if not np.all(np.isfinite(r0)):
+        info["status"] = EINVAL
+        return X, info
+    if np.all(r0 == 0.0):
+        return X, info
+    if np.any(r0 == 0.0) and not decoupled_columns(variant, p):
+        info["status"] = EINVAL
+        return X, info
+    safe = np.where(r0 == 0.0, 1.0, r0)
+    prev = np.inf
+    for outer in range(1, maxit + 1):
+        c = np.sqrt(np.einsum("ij,ij->j", R, R))
+        ratio = float(np.max(np.where(r0 == 0.0, 0.0, c / safe)))
+        if ratio <= tol:
+            info["true_ratio"] = ratio
+            return X, info
+        if ratio > 0.5 * prev:
+            X, sub = solve64(A, B, variant, p, tol, maxit=100000, X0=X, ref_norms=r0)
+            info["fp64_fallback"] = True
+            info["iterations"] += sub["iterations"]
+            info["status"] = sub["status"]
+            return X, info
+        prev = ratio
+        s = float(np.max(c))
+        D, its, st = inner_solve32(A32, (R / s).astype(np.float32), variant, p, inner_tol, inner_maxit)
+        info["iterations"] += its
+        info["outer_iterations"] = outer
+        if st < 0:
+            X, sub = solve64(A, B, variant, p, tol, maxit=100000, X0=X, ref_norms=r0)
+            info["fp64_fallback"] = True
+            info["iterations"] += sub["iterations"]
+            info["status"] = sub["status"]
+            return X, info
+        X = X + s * D.astype(np.float64)
+        R = B - A @ X
+    info["status"] = NOT_CONVERGED
+    return X, info

@@ -1,0 +1,93 @@
+"""Planted mistakes in the oracle must be caught by its pins (CPU only).
+
+Each case monkeypatches one step of the oracle's Algorithm 1 with a plausible
+error (wrong sign, transposed coefficient, wrong side of a solve, interleaved
+column groups, dropped symmetric half) and checks that the independent
+trace-A-norm Galerkin characterisation (or textbook CG) rejects it.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import oracle.bcg as ob
+from oracle.stencil import stencil_csr
+from tests.galerkin import galerkin_iterate
+from workload import cell_coefficients, rhs
+
+
+def _setup():
+    A = stencil_csr(2, 7, cell_coefficients(2, 7, 1.0))
+    B = rhs(A.shape[0], 4, "uniform")
+    X0 = np.zeros_like(B)
+    return A, B, X0
+
+
+def _galerkin_mismatch(variant, p, m=3):
+    A, B, X0 = _setup()
+    X, _ = ob.solve(A, B, variant, p, tol=0.0, maxit=m, X0=X0)
+    Xg = galerkin_iterate(A, B, X0, variant, p, m)
+    return np.linalg.norm(X - Xg) / np.linalg.norm(Xg)
+
+
+def test_unmutated_passes():
+    for v, p in [("block", 4), ("hybrid", 2), ("global", 2), ("parallel", 1)]:
+        assert _galerkin_mismatch(v, p) < 1e-9
+
+
+def _apply_transposed(Y, C, p):
+    return _orig_apply(Y, np.transpose(C, (0, 2, 1)).copy(), p)
+
+
+_orig_apply = ob.apply_coeff
+_orig_product = ob.block_product
+_orig_beta = ob.solve_beta
+
+
+def _interleaved_product(X, Y, variant, p):
+    k = X.shape[1]
+    q = k // p
+    perm = np.array([g + q * a for g in range(q) for a in range(p)])  # groups {g, g+q, ...}
+    return _orig_product(X[:, perm], Y[:, perm], variant, p)
+
+
+def _beta_wrong_side(rho_old, rho_new, dec):
+    out = np.empty_like(rho_new)
+    for g in range(rho_old.shape[0]):
+        out[g] = rho_new[g] @ np.linalg.inv(rho_old[g])
+    return out
+
+
+def _product_upper_only(X, Y, variant, p):
+    G = _orig_product(X, Y, variant, p)
+    return np.triu(G)
+
+
+@pytest.mark.parametrize("mutation,variant,p", [
+    ("transposed_coefficients", "block", 4),
+    ("interleaved_groups", "hybrid", 2),
+    ("interleaved_groups", "global", 2),
+    ("beta_wrong_side", "block", 4),
+    ("upper_triangle_gram", "block", 4),
+])
+def test_mutation_is_caught(monkeypatch, mutation, variant, p):
+    if mutation == "transposed_coefficients":
+        monkeypatch.setattr(ob, "apply_coeff", _apply_transposed)
+    elif mutation == "interleaved_groups":
+        monkeypatch.setattr(ob, "block_product", _interleaved_product)
+    elif mutation == "beta_wrong_side":
+        monkeypatch.setattr(ob, "solve_beta", _beta_wrong_side)
+    elif mutation == "upper_triangle_gram":
+        monkeypatch.setattr(ob, "block_product", _product_upper_only)
+    assert _galerkin_mismatch(variant, p) > 1e-6
+
+
+def test_minus_sign_update_is_caught(monkeypatch):
+    # Replace line 13 by P <- R - P beta through a negated beta.
+    def neg_beta(rho_old, rho_new, dec):
+        return -_orig_beta(rho_old, rho_new, dec)
+    monkeypatch.setattr(ob, "solve_beta", neg_beta)
+    A, B, _ = _setup()
+    x2, _ = spla.cg(A, B[:, 0], x0=np.zeros(A.shape[0]), rtol=0.0, atol=0.0, maxiter=3)
+    X, _ = ob.solve(A, B[:, :1], "block", 0, tol=0.0, maxit=3)
+    assert np.linalg.norm(X[:, 0] - x2) > 1e-6 * np.linalg.norm(x2)
+    assert _galerkin_mismatch("block", 4) > 1e-6
