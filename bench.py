@@ -1,0 +1,228 @@
+"""Benchmark: right-hand-side solves per second of block CG on one MI355X.
+
+A step is one complete solve A X = B from X = 0 to the stop rule (every
+column's residual reduced by 1e-8) of the synthetic 3D 7-point Poisson
+system on a 128^3 grid with k = 16 uniform right-hand sides, with every
+kernel of the iteration on the GPU and B, X, A resident in HBM before the
+timed region. value = k * steps / wall time.
+
+Also reported on the same JSON line:
+  roofline      the dominant kernel's algorithmic bytes per launch over its
+                event-measured average duration (events on the library's
+                stream, launches that returned at entry excluded);
+  cpu_baseline  the FP64 CPU oracle on this host: a bounded number of its
+                iterations on the same full-size system, scaled to the
+                GPU's iteration count;
+  kernels       per-class time breakdown of one extra profiled solve.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RHS-solves/s to 1e-8 rel residual (FP32+refine vs FP64) + achieved HBM GB/s"
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(cls: str, n: int, nnz: int, k: int, precision: str) -> float:
+    """Bytes one launch of a kernel class must move (each operand once)."""
+    vb = 4 if precision == "fp32_refine" else 8
+    if cls == "spmm":            # A (values + column index + row pointer), P read, Q written
+        return vb * nnz + 4 * nnz + 4 * (n + 1) + 2 * vb * n * k
+    if cls == "update_xr":       # X, P, Q, R read; X, R written
+        return 6 * vb * n * k
+    if cls == "update_p":        # P, R read; P written
+        return 3 * vb * n * k
+    raise ValueError(cls)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1912_11930_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1912_11930_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str, variant: str, precision: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if current."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))[f"{kernel}/{workload}/{variant}/{precision}"]
+    except (KeyError, ValueError):
+        return None
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(w, variant: str, p: int, gpu_iterations: int, budget_s: float):
+    """Time the oracle's iterations on the full system; scale to the solve."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle.bcg import solve as oracle_solve
+    from oracle.stencil import stencil_csr
+    from workload import coefficients_for, rhs_for
+
+    A = stencil_csr(w.dim, w.N, coefficients_for(w))
+    B = rhs_for(w)
+    # one iteration to calibrate, then as many as fit the budget
+    t0 = time.perf_counter()
+    oracle_solve(A, B, variant, p, tol=0.0, maxit=1)
+    t1 = time.perf_counter() - t0
+    m = max(2, min(gpu_iterations, int(budget_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    _, info = oracle_solve(A, B, variant, p, tol=0.0, maxit=m)
+    tm = time.perf_counter() - t0
+    per_it = tm / m
+    t_solve = per_it * gpu_iterations
+    blas = [d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"]
+    cores = max(blas + [1])
+    return {
+        "value": w.k / t_solve,
+        "unit": "RHS-solves/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"{m} iterations of the FP64 NumPy/SciPy oracle ({variant}, p={p}) on the full "
+                   f"{w.name} system ({tm:.1f} s, {per_it * 1e3:.0f} ms/iteration), scaled to the GPU's "
+                   f"{gpu_iterations} iterations; sparse product single-threaded, BLAS on {cores} threads, "
+                   f"host has {os.cpu_count()} logical CPUs"),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="poisson3d_128_k16")
+    ap.add_argument("--variant", default="block")
+    ap.add_argument("--p", type=int, default=0)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_refine"])
+    ap.add_argument("--tol", type=float, default=None)
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        log("bench.py: only --gpus 1 is supported (single-GPU build; see DESIGN.md for the sharding design)")
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1912_11930_amd as P
+    from paper_1912_11930_amd import _capi
+    from workload import WORKLOADS, coefficients_for, rhs_for
+
+    w = WORKLOADS[args.workload]
+    tol = w.tol if args.tol is None else args.tol
+    dev = torch.device("cuda:0")
+    kappa = coefficients_for(w)
+    rp, ci, va = P.stencil(w.dim, w.N, None if kappa is None else torch.from_numpy(kappa).to(dev), device=dev)
+    B = torch.from_numpy(rhs_for(w)).to(dev)
+    n, k, nnz = w.n, w.k, w.nnz
+    solver = P.BCG(rp, ci, va, k=k, subalgebra=args.variant, p=args.p)
+    if args.precision != "fp64":
+        solver.set_precision(args.precision)
+    p_eff = {"block": k, "parallel": 1}.get(args.variant, args.p or 1)
+    X = torch.empty_like(B)
+    torch.cuda.synchronize()
+    log(f"bench: {w.name} n={n} nnz={nnz} k={k} variant={args.variant} p={p_eff} precision={args.precision}")
+
+    # warm-up solves; the last one profiles every kernel class for the breakdown
+    info = None
+    for i in range(max(args.warmup, 1)):
+        if i == max(args.warmup, 1) - 1:
+            solver.set_profiling(True)
+        X.zero_()
+        _, info = solver.solve(B, X, tol=tol, maxit=100000)
+        log(f"warmup {i}: status={info['status_name']} iterations={info['iterations']} "
+            f"{info['solve_ms']:.1f} ms true_rel_res={info['true_rel_res']:.2e}")
+    breakdown = solver.kernel_times()
+    solver.set_profiling(False)
+    cand = {c: breakdown[c][1] for c in ("spmm", "update_xr", "update_p")}
+    dominant = max(cand, key=cand.get)
+
+    # timed region: events only around the dominant kernel class
+    solver.set_profiling(True, classes=[dominant])
+    its = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        X.zero_()
+        _, info = solver.solve(B, X, tol=tol, maxit=100000)
+        its.append(info["iterations"])
+        log(f"step {i}: status={info['status_name']} iterations={info['iterations']} {info['solve_ms']:.1f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    launches, total_ms = solver.kernel_times()[dominant]
+    solver.set_profiling(False)
+
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = k * args.steps / elapsed
+    avg_ms = total_ms / max(launches, 1)
+    bytes_launch = algorithmic_bytes(dominant, n, nnz, k, args.precision)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dominant, w.name, args.variant, args.precision)
+
+    total_known = sum(v[1] for v in breakdown.values())
+    kernels = {c: {"launches": breakdown[c][0], "total_ms": round(breakdown[c][1], 3),
+                   "avg_us": round(1e3 * breakdown[c][1] / max(breakdown[c][0], 1), 2)}
+               for c in _capi.KERNEL_CLASSES if breakdown[c][0]}
+    for c in ("spmm", "update_xr", "update_p"):
+        if c in kernels:
+            b = algorithmic_bytes(c, n, nnz, k, args.precision)
+            kernels[c]["GBps"] = round(b / (kernels[c]["avg_us"] * 1e-6) / 1e9, 1)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "RHS-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": f"{w.N}^{w.dim}", "n": n, "nnz": nnz, "k": k,
+                   "variant": args.variant, "p": p_eff, "precision": args.precision, "tol": tol,
+                   "rhs": w.rhs},
+        "iterations": its[-1] if its else None,
+        "true_rel_res": info["true_rel_res"] if info else None,
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "bytes_per_launch": bytes_launch, "avg_launch_us": 1e3 * avg_ms,
+                     "launches": launches},
+        "kernels": kernels,
+        "kernels_total_ms": round(total_known, 3),
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu_baseline: timing the oracle ...")
+        out["cpu_baseline"] = cpu_baseline(w, args.variant, p_eff, its[-1] if its else 1, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,240 @@
+/*
+ * bcg.h -- C ABI of the MI355X (gfx950) block Conjugate Gradients library.
+ *
+ * Solves A X = B for a sparse symmetric positive definite A (n x n, CSR) and
+ * k right-hand sides (Dreier & Engwer, "Strategies for the vectorized Block
+ * Conjugate Gradients method", Section 1 problem statement), with the
+ * stabilised block CG of Algorithm 1 (Section 3) and the preconditioner
+ * M = I, over one of the *-subalgebras of Section 2:
+ *
+ *   BCG_BLOCK    classical block CG, S = R^{k x k}             (p = k)
+ *   BCG_GLOBAL   S = R^{p x p} (x) I_q, one p x p coefficient shared by the
+ *                q = k/p contiguous column groups              (p | k)
+ *   BCG_PARALLEL S = diag(R^k), k independent CGs in lockstep  (p = 1)
+ *   BCG_HYBRID   S = diag(R^{p x p}, ..., R^{p x p}), q independent
+ *                p-column block CGs                            (p | k)
+ *
+ * Memory, layout and ownership
+ *   - Every array argument is a DEVICE pointer on the GPU that was current
+ *     when the handle was created, unless a comment says "host".
+ *   - Block vectors (B, X, Y, G) are n x k, row-major, k fastest (element
+ *     (i, j) at offset i*k + j), FP64. This is the paper's layout with the
+ *     right-hand-side index innermost (Section 4).
+ *   - CSR: rowptr int32[n+1] (rowptr[0] = 0, non-decreasing, rowptr[n] = nnz),
+ *     colind int32[nnz] in [0, n), values FP64[nnz]. Indices are int32, so
+ *     nnz must be below 2^31.
+ *   - bcg_create copies the CSR into library-owned device memory (plus an FP32
+ *     copy of the values); the caller may free its arrays afterwards. The
+ *     handle owns its workspace (residual, search directions, products,
+ *     reduction partials), allocated at create (and, for the FP32-refinement
+ *     mode, on the first solve in that mode).
+ *   - Caller-owned arrays are borrowed for the duration of a call only.
+ *
+ * Streams and synchronisation
+ *   - All device work of a handle is enqueued on the stream given to
+ *     bcg_set_stream (default: the null stream). bcg_solve returns only after
+ *     its work on that stream has finished. The other calls taking device
+ *     pointers are stream-ordered and return after enqueueing.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *
+ * Errors
+ *   - Calls return a status code (BCG_OK = 0; negative = error). The text of
+ *     the last error of the calling thread is returned by bcg_last_error().
+ */
+#ifndef BCG_H
+#define BCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define BCG_OK 0
+#define BCG_NOT_CONVERGED 1 /* maxit reached; X holds the last iterate */
+#define BCG_EINVAL (-1)     /* invalid argument or input (see each call)  */
+#define BCG_EBREAKDOWN (-2) /* numerical breakdown; X holds the last iterate */
+#define BCG_ENOMEM (-3)     /* device allocation failed */
+#define BCG_EHIP (-4)       /* HIP runtime error */
+
+typedef enum {
+  BCG_BLOCK = 0,
+  BCG_GLOBAL = 1,
+  BCG_PARALLEL = 2,
+  BCG_HYBRID = 3
+} bcg_subalgebra;
+
+typedef enum {
+  BCG_FP64 = 0,       /* everything in FP64 */
+  BCG_FP32_REFINE = 1 /* FP32 inner block CG (FP64 block products and small
+                         solves), FP64 outer iterative refinement */
+} bcg_precision;
+
+typedef struct bcg_handle bcg_handle;
+
+/* Sparse matrix in CSR form (device pointers; see the layout notes above). */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int32_t *rowptr;
+  const int32_t *colind;
+  const double *values;
+} bcg_csr;
+
+/* Result summary of the last bcg_solve (host struct). */
+typedef struct {
+  int32_t status;           /* return value of the last bcg_solve */
+  int32_t iterations;       /* products A*P, summed over inner solves */
+  int32_t outer_iterations; /* refinement steps (0 in FP64 mode) */
+  int32_t converged;        /* 1 if the stop rule was met */
+  int32_t fp64_fallback;    /* refinement stagnated and finished in FP64 */
+  int32_t k;
+  double max_rel_res;       /* max_j ||R_j|| / ||R0_j|| at exit: the recursive
+                               residual (FP64 mode) or the FP64 true residual
+                               (refinement mode) */
+  double true_rel_res;      /* max_j ||(B - A X)_j|| / ||R0_j|| after the
+                               solve, recomputed in FP64 */
+  double solve_ms;          /* wall time spent inside bcg_solve */
+} bcg_info;
+
+/*
+ * bcg_create -- build a solver for A with k right-hand sides.
+ *   A           CSR of an SPD matrix (device arrays, copied).
+ *   k           1 <= k <= 256.
+ *   subalgebra  one of bcg_subalgebra.
+ *   p           block size: BLOCK p in {0, k}; PARALLEL p in {0, 1};
+ *               GLOBAL p = 0 (means 1) or 1 <= p <= k with k % p == 0;
+ *               HYBRID 1 <= p <= k with k % p == 0.
+ *   out         host pointer receiving the new handle.
+ * Returns BCG_EINVAL for invalid n, nnz, k, subalgebra or p (the CSR
+ * contents are trusted: indices must be in range), BCG_ENOMEM, BCG_EHIP.
+ * Section 2 (subalgebra definitions) fixes the admissible p.
+ */
+int bcg_create(const bcg_csr *A, int k, int subalgebra, int p, bcg_handle **out);
+
+/* Releases the handle and everything it owns. NULL is ignored. */
+void bcg_destroy(bcg_handle *h);
+
+/* Sets the HIP stream (a hipStream_t, e.g. torch's current stream) used by
+ * every later call on this handle. NULL selects the null stream. */
+int bcg_set_stream(bcg_handle *h, void *hip_stream);
+
+/*
+ * bcg_set_precision -- choose FP64 or FP32 inner solves with FP64 refinement.
+ *   inner_tol    relative residual reduction of each inner FP32 solve
+ *                (0 < inner_tol < 1; default 1e-4).
+ *   inner_maxit  iteration cap of each inner solve (>= 1; default 1000).
+ *   max_outer    cap on refinement steps (>= 1; default 50).
+ * Not in the paper: the mixed-precision form keeps the block products, the
+ * Cholesky and LU solves and the true residual in FP64.
+ */
+int bcg_set_precision(bcg_handle *h, int mode, double inner_tol, int inner_maxit, int max_outer);
+
+/*
+ * bcg_solve -- run Algorithm 1 (M = I) on A X = B.
+ *   B      n x k right-hand sides (read).
+ *   X      n x k initial guess on entry, solution on exit (read/write; may
+ *          not alias B).
+ *   tol    stop when every column's residual norm fell below tol times its
+ *          initial residual norm (Section 4 stop rule, 2-norm of the
+ *          recursive residual, checked after the residual update). tol = 0
+ *          runs exactly maxit iterations.
+ *   maxit  iteration cap (>= 0); in refinement mode the cap of each FP64
+ *          fallback.
+ * Returns BCG_OK (converged, or B - A X0 = 0), BCG_NOT_CONVERGED,
+ * BCG_EINVAL (non-finite B or X0, or a zero initial-residual column in a
+ * subalgebra other than the diagonal one: PARALLEL, or HYBRID with p = 1),
+ * BCG_EBREAKDOWN (a Cholesky pivot of the symmetrised alpha not above
+ * p*eps times its diagonal, a zero LU pivot of rho, or a non-finite
+ * residual), BCG_EHIP. Synchronous with respect to the handle's stream.
+ */
+int bcg_solve(bcg_handle *h, const double *B, double *X, double tol, int maxit);
+
+/* Copies new matrix values (same pattern as at create; device array of nnz
+ * FP64) into the handle, e.g. for a differentiable solve. Stream-ordered. */
+int bcg_update_values(bcg_handle *h, const double *values);
+
+/*
+ * bcg_csr_outer -- sampled outer product on the pattern of A:
+ *   out_vals[e] = alpha * sum_c Y[row(e), c] * X[col(e), c], e < nnz.
+ * With Y = A^{-1} G and alpha = -1 this is dL/d(values of A) for a loss
+ * with dL/dX = G (adjoint of the solve). Y, X: n x k FP64; out_vals: FP64[nnz]
+ * (written, not accumulated). Stream-ordered.
+ */
+int bcg_csr_outer(bcg_handle *h, const double *Y, const double *X, double alpha, double *out_vals);
+
+/* Copies the summary of the last solve into *info (host struct). */
+int bcg_get_info(const bcg_handle *h, bcg_info *info);
+
+/* Copies the k per-column final ratios ||R_j|| / ||R0_j|| of the last solve
+ * into host array ratios[k]. */
+int bcg_get_column_ratios(const bcg_handle *h, double *ratios, int k);
+
+/*
+ * Per-kernel-class timing (not in the paper; measurement support). When
+ * enabled, HIP events are recorded on the handle's stream around every
+ * launch, and the durations of launches that did work (iterations up to the
+ * one the stop rule accepted; launches that returned at entry after the stop
+ * are excluded) are accumulated per class until profiling is enabled again.
+ */
+enum {
+  BCG_K_SPMM = 0,      /* Q = A P with the partial <<P, Q>>              */
+  BCG_K_UPDATE_XR = 1, /* X += P lambda, R -= Q lambda, <<R, R>>, norms  */
+  BCG_K_UPDATE_P = 2,  /* P = R + P beta with the partial <<P, R>>      */
+  BCG_K_REDUCE = 3,    /* fixed-order sums of the per-workgroup partials */
+  BCG_K_SMALL = 4,     /* Cholesky / LU solves and the stop rule         */
+  BCG_K_RESIDUAL = 5,  /* B - A X, FP32 start of a refinement step, X += s D */
+  BCG_K_PRODUCT = 6,   /* stand-alone block products (large p)           */
+  BCG_NUM_KERNEL_CLASSES = 7
+};
+
+typedef struct {
+  int64_t launches; /* counted launches */
+  double total_ms;  /* summed event-measured durations */
+} bcg_kernel_time;
+
+/* enable: bit mask of classes to record (1 << BCG_K_*; -1 = all); a non-zero
+ * mask resets the counters and starts recording, 0 stops. */
+int bcg_set_profiling(bcg_handle *h, int enable);
+
+/* Copies min(count, BCG_NUM_KERNEL_CLASSES) classes into out (host). */
+int bcg_get_kernel_times(const bcg_handle *h, bcg_kernel_time *out, int count);
+
+/* Text of the calling thread's last error ("" if none). Host string owned
+ * by the library, valid until the next failing call on this thread. */
+const char *bcg_last_error(void);
+
+/*
+ * Stencil matrices (the paper's test problem class, Section 4: heterogeneous
+ * Poisson with a 5-point finite-difference stencil; 7-point in 3D).
+ * Interior grid of N^dim points, Dirichlet neighbours eliminated,
+ * lexicographic order with x fastest, ascending columns per row. Without
+ * coefficients: 2*dim on the diagonal, -1 off it. With per-cell coefficients
+ * kappa (FP64[N^dim]): interior face value ((2*ka)*kb)/(ka+kb), boundary
+ * face value kappa of the cell, off-diagonal -face, diagonal = sum of the
+ * cell's face values in the order x-, x+, y-, y+, z-, z+ (IEEE FP64, each
+ * operation rounded once).
+ */
+
+/* Number of stored entries, (2*dim+1)*N^dim - 2*dim*N^(dim-1), or -1 for
+ * dim not in {2, 3}, N < 1, or nnz / n beyond int32. Host-only. */
+int64_t bcg_stencil_nnz(int dim, int N);
+
+/* Writes rowptr int32[n+1], colind int32[nnz], values FP64[nnz] (device,
+ * caller-allocated). kappa may be NULL (constant coefficient 1). Stream-
+ * ordered on hip_stream (NULL = null stream). */
+int bcg_stencil_build(int dim, int N, const double *kappa, int32_t *rowptr, int32_t *colind,
+                      double *values, void *hip_stream);
+
+/* Transpose Jacobian of the stencil values with respect to kappa:
+ * dkappa[c] = sum_e dvalues[e] * d values[e] / d kappa[c] (device arrays;
+ * dvalues in the CSR order of bcg_stencil_build). Stream-ordered. */
+int bcg_stencil_kappa_vjp(int dim, int N, const double *kappa, const double *dvalues,
+                          double *dkappa, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BCG_H */

@@ -1,0 +1,82 @@
+// Internal declarations shared by the block CG kernels and the solver runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace bcg {
+
+constexpr int kBlock = 256;        // threads per workgroup of the row kernels
+constexpr int kTileElems = 1024;   // rows*k elements staged per LDS tile
+constexpr int kMaxWG = 1024;       // cap on workgroups of the row kernels
+constexpr int kNabMax = 8;         // entry blocks per thread in fused products
+constexpr int kLamLds = 2048;      // coefficient entries kept in LDS
+
+// Device-side solve state. Every per-iteration kernel returns at entry once
+// `done` is set, which freezes X at the iterate the stop rule accepted.
+struct DevState {
+  int done;
+  int status;
+  int iter;
+  int pad;
+  double max_ratio;  // largest column ratio ||R_j|| / r0_j after the last iteration
+};
+
+// Geometry of one solve: the subalgebra, the packed product layout and the
+// thread plan of the block-product accumulation.
+struct Plan {
+  int64_t n;
+  int k, p, q;
+  int qo;       // packed blocks: 1 for the global subalgebra, q otherwise
+  int global;   // 1: product summed over the q groups
+  int dec;      // 1: p = 1 with independent columns (zero lanes allowed)
+  int E;        // qo * p * p packed product entries
+  int W;        // partial row width = E + k (product | column norms)
+  int rb;       // register block of the product accumulation (1 or 2)
+  int pb;       // p / rb
+  int EB;       // entry blocks = qo * pb * pb
+  int S;        // row slices when EB < kBlock
+  int nab;      // entry blocks per thread when EB > kBlock
+  int fused;    // 1: product accumulated inside the producing kernel
+  int TR;       // rows per LDS tile
+  int64_t ntiles;
+  int nwg;      // workgroups of the row kernels
+};
+
+Plan make_plan(int64_t n, int k, int p, int global, int dec);
+
+// ---- launchers (all enqueue on `s`; none synchronises) ----
+// R = B - A X; norms partial; if with_p: P = R and <<R,R>> partial.
+void launch_residual(const Plan& pl, const int32_t* rowptr, const int32_t* colind, const double* vals,
+                     const double* B, const double* X, double* R, double* P, double* part,
+                     int with_p, hipStream_t s);
+// FP32 inner start: s = max_j sqrt(norms_j); R32 = R64/s; P32 = R32; D32 = 0;
+// <<R32,R32>> partial (FP64 accumulation) and norms partial.
+void launch_cast_init(const Plan& pl, const double* R64, const double* norms, float* R32, float* P32,
+                      float* D32, double* scale, double* part, hipStream_t s);
+template <typename T>
+void launch_spmm_product(const Plan& pl, const int32_t* rowptr, const int32_t* colind, const T* vals,
+                         const T* P, T* Q, double* part, const DevState* st, hipStream_t s);
+template <typename T>
+void launch_update_xr(const Plan& pl, T* X, T* R, const T* P, const T* Q, const T* lam, double* part,
+                      const DevState* st, hipStream_t s);
+template <typename T>
+void launch_update_p(const Plan& pl, T* P, const T* R, const T* beta, double* part, const DevState* st,
+                     hipStream_t s);
+// stand-alone product for plans whose products do not fit the fused path
+template <typename T>
+void launch_product(const Plan& pl, const T* X, const T* Y, double* part, const DevState* st, hipStream_t s);
+void launch_reduce(const Plan& pl, const double* part, double* out, int width, const DevState* st,
+                   hipStream_t s);
+void launch_solve_lambda(const Plan& pl, const double* alpha, const double* rho, double* lam, float* lam32,
+                         double* ws, DevState* st, hipStream_t s);
+void launch_conv_beta(const Plan& pl, const double* red_new, const double* r0, const double* rho_old,
+                      double* beta, float* beta32, double* ws, double* ratios, DevState* st, double tol,
+                      int it, int maxit, hipStream_t s);
+void launch_axpy_scaled(int64_t count, double* X, const float* D, const double* scale, hipStream_t s);
+void launch_sampled_outer(int64_t n, int k, const int32_t* rowptr, const int32_t* colind, const double* Y,
+                          const double* X, double alpha, double* out, hipStream_t s);
+void launch_cast_values(int64_t nnz, const double* v, float* v32, hipStream_t s);
+
+}  // namespace bcg

@@ -1,0 +1,888 @@
+// Block CG kernels for gfx950 (generic path).
+//
+// One iteration of Algorithm 1 (Section 3, M = I) is five row-parallel passes
+// over the n x k block vectors (row-major, k fastest) plus small reductions
+// and solves:
+//   spmm_product : Q = A P                      and partial alpha = <<P, Q>>_S
+//   solve_lambda : lambda = sym(alpha)^{-1} rho  (Cholesky per group)
+//   update_xr    : X += P lambda, R -= Q lambda  and partial <<R, R>>_S, ||R_j||^2
+//   conv_beta    : stop rule, beta = rho^{-1} rho_new (LU with partial pivoting)
+//   update_p     : P = R + P beta               and partial rho = <<P, R>>_S
+// so every block product is accumulated by the kernel that produces its
+// operands (the paper notes the recomputed rho can share a reduction with the
+// product before it, Section 3). The partial products of each workgroup are
+// summed in a fixed order by `reduce`, so results are bitwise reproducible.
+//
+// Block products <<X, Y>>_S (Section 2): the q diagonal p x p blocks
+// X_g^T Y_g of X^T Y (hybrid / block / parallel), or their sum (global), in
+// the packed layout [qo][p][p].
+#include <cfloat>
+#include <type_traits>
+#include <cmath>
+
+#include "../../include/bcg.h"
+#include "bcg_internal.h"
+
+namespace bcg {
+
+namespace {
+
+__device__ __forceinline__ bool stopped(const DevState* st) {
+  return st != nullptr && *reinterpret_cast<const volatile int*>(&st->done) != 0;
+}
+
+__device__ __forceinline__ void set_status(DevState* st, int status) {
+  *reinterpret_cast<volatile int*>(&st->status) = status;
+  *reinterpret_cast<volatile int*>(&st->done) = 1;
+}
+
+// ------------------------------------------------------------------------
+// Block-product accumulation over LDS tiles.
+//
+// Entry block eb = (g, A, Bb) owns the RB x RB entries
+// (a, b) = (A*RB + i, Bb*RB + j) of packed block g. When there are fewer
+// entry blocks than threads, the rows of a tile are split into S slices.
+// ------------------------------------------------------------------------
+template <int RB, int NAB>
+struct Acc {
+  double v[NAB][RB][RB];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int j = 0; j < NAB; ++j)
+#pragma unroll
+      for (int a = 0; a < RB; ++a)
+#pragma unroll
+        for (int b = 0; b < RB; ++b) v[j][a][b] = 0.0;
+  }
+};
+
+__device__ __forceinline__ void decode_eb(const Plan& pl, int eb, int& g, int& A, int& Bb) {
+  const int pp = pl.pb * pl.pb;
+  g = eb / pp;
+  const int r = eb - g * pp;
+  A = r / pl.pb;
+  Bb = r - A * pl.pb;
+}
+
+template <typename T, int RB>
+__device__ __forceinline__ void acc_rows(double (&acc)[RB][RB], const T* Xs, const T* Ys, const Plan& pl,
+                                         int g, int A, int Bb, int r0, int rows, int rstep) {
+  const int k = pl.k, p = pl.p;
+  const int g0 = pl.global ? 0 : g;
+  const int g1 = pl.global ? pl.q : g + 1;
+  for (int r = r0; r < rows; r += rstep) {
+    const T* xr = Xs + r * k + A * RB;
+    const T* yr = Ys + r * k + Bb * RB;
+    for (int gg = g0; gg < g1; ++gg) {
+      double x[RB], y[RB];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        x[i] = static_cast<double>(xr[gg * p + i]);
+        y[i] = static_cast<double>(yr[gg * p + i]);
+      }
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < RB; ++j) acc[i][j] = fma(x[i], y[j], acc[i][j]);
+    }
+  }
+}
+
+// Accumulates entry blocks [eb_off, eb_lim) of <<Xs, Ys>> over `rows` rows.
+template <typename T, int RB, int NAB>
+__device__ __forceinline__ void product_tile(Acc<RB, NAB>& acc, const T* Xs, const T* Ys, int rows,
+                                             const Plan& pl, int tid, int eb_off, int eb_lim) {
+  if (pl.EB <= kBlock) {
+    if (tid < pl.S * pl.EB) {
+      const int eb = tid % pl.EB, s = tid / pl.EB;
+      int g, A, Bb;
+      decode_eb(pl, eb, g, A, Bb);
+      acc_rows<T, RB>(acc.v[0], Xs, Ys, pl, g, A, Bb, s, rows, pl.S);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < NAB; ++j) {
+      const int eb = eb_off + tid + j * kBlock;
+      if (eb < eb_lim) {
+        int g, A, Bb;
+        decode_eb(pl, eb, g, A, Bb);
+        acc_rows<T, RB>(acc.v[j], Xs, Ys, pl, g, A, Bb, 0, rows, 1);
+      }
+    }
+  }
+}
+
+// Writes the workgroup's partial product (slices summed in a fixed order).
+template <int RB, int NAB>
+__device__ void product_finish(const Acc<RB, NAB>& acc, double* prow, const Plan& pl, double* scratch,
+                               int tid, int eb_off, int eb_lim) {
+  const int p = pl.p;
+  if (pl.EB <= kBlock) {
+    const bool active = tid < pl.S * pl.EB;
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int j = 0; j < RB; ++j) scratch[(tid * RB + i) * RB + j] = active ? acc.v[0][i][j] : 0.0;
+    __syncthreads();
+    if (tid < pl.EB) {
+      int g, A, Bb;
+      decode_eb(pl, tid, g, A, Bb);
+      for (int i = 0; i < RB; ++i)
+        for (int j = 0; j < RB; ++j) {
+          double s = 0.0;
+          for (int sl = 0; sl < pl.S; ++sl) s += scratch[((sl * pl.EB + tid) * RB + i) * RB + j];
+          prow[(int64_t)g * p * p + (A * RB + i) * p + Bb * RB + j] = s;
+        }
+    }
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int jb = 0; jb < NAB; ++jb) {
+      const int eb = eb_off + tid + jb * kBlock;
+      if (eb < eb_lim) {
+        int g, A, Bb;
+        decode_eb(pl, eb, g, A, Bb);
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+          for (int j = 0; j < RB; ++j) prow[(int64_t)g * p * p + (A * RB + i) * p + Bb * RB + j] = acc.v[jb][i][j];
+      }
+    }
+  }
+}
+
+// Column sums of squares of an LDS tile (k <= kBlock).
+template <typename T>
+__device__ __forceinline__ void norms_tile(double& acc, const T* Rs, int rows, int k, int tid) {
+  const int sn = kBlock / k;
+  if (tid < sn * k) {
+    const int c = tid % k, s = tid / k;
+    for (int r = s; r < rows; r += sn) {
+      const double v = static_cast<double>(Rs[r * k + c]);
+      acc = fma(v, v, acc);
+    }
+  }
+}
+
+__device__ void norms_finish(double acc, double* out, int k, double* scratch, int tid) {
+  scratch[tid] = acc;
+  __syncthreads();
+  if (tid < k) {
+    const int sn = kBlock / k;
+    double s = 0.0;
+    for (int sl = 0; sl < sn; ++sl) s += scratch[sl * k + tid];
+    out[tid] = s;
+  }
+  __syncthreads();
+}
+
+struct TileRange {
+  int64_t row0, base;
+  int rows, ne;
+};
+
+__device__ __forceinline__ TileRange tile_range(const Plan& pl, int64_t t) {
+  TileRange tr;
+  tr.row0 = t * pl.TR;
+  const int64_t left = pl.n - tr.row0;
+  tr.rows = static_cast<int>(left < pl.TR ? left : pl.TR);
+  tr.ne = tr.rows * pl.k;
+  tr.base = tr.row0 * pl.k;
+  return tr;
+}
+
+// ------------------------------------------------------------------------
+// Row kernels
+// ------------------------------------------------------------------------
+
+// R = B - A X (FP64); P = R and <<R, R>> partial when with_p; column norms.
+template <int RB, int NAB>
+__global__ __launch_bounds__(kBlock) void k_residual(Plan pl, const int32_t* __restrict__ rowptr,
+                                                     const int32_t* __restrict__ colind,
+                                                     const double* __restrict__ vals,
+                                                     const double* __restrict__ B, const double* __restrict__ X,
+                                                     double* __restrict__ R, double* __restrict__ P,
+                                                     double* __restrict__ part, int with_p) {
+  __shared__ double Rs[kTileElems];
+  __shared__ double scratch[kBlock * RB * RB];
+  const int tid = threadIdx.x, k = pl.k;
+  Acc<RB, NAB> acc;
+  acc.zero();
+  double nacc = 0.0;
+  const bool prod = with_p && pl.fused;
+  for (int64_t t = blockIdx.x; t < pl.ntiles; t += gridDim.x) {
+    const TileRange tr = tile_range(pl, t);
+    for (int e = tid; e < tr.ne; e += kBlock) {
+      const int r = e / k, c = e - r * k;
+      const int64_t i = tr.row0 + r;
+      double s = 0.0;
+      const int j1 = rowptr[i + 1];
+      for (int j = rowptr[i]; j < j1; ++j) s = fma(vals[j], X[(int64_t)colind[j] * k + c], s);
+      const double v = B[tr.base + e] - s;
+      R[tr.base + e] = v;
+      if (with_p) P[tr.base + e] = v;
+      Rs[e] = v;
+    }
+    __syncthreads();
+    if (prod) product_tile<double, RB, NAB>(acc, Rs, Rs, tr.rows, pl, tid, 0, pl.EB);
+    norms_tile<double>(nacc, Rs, tr.rows, k, tid);
+    __syncthreads();
+  }
+  double* prow = part + (int64_t)blockIdx.x * pl.W;
+  if (prod) product_finish<RB, NAB>(acc, prow, pl, scratch, tid, 0, pl.EB);
+  norms_finish(nacc, prow + pl.E, k, scratch, tid);
+}
+
+// FP32 inner start of a refinement step.
+template <int RB, int NAB>
+__global__ __launch_bounds__(kBlock) void k_cast_init(Plan pl, const double* __restrict__ R64,
+                                                      const double* __restrict__ norms, float* __restrict__ R32,
+                                                      float* __restrict__ P32, float* __restrict__ D32,
+                                                      double* __restrict__ scale, double* __restrict__ part) {
+  __shared__ float Rs[kTileElems];
+  __shared__ double scratch[kBlock * RB * RB];
+  __shared__ double s_sh;
+  const int tid = threadIdx.x, k = pl.k;
+  if (tid == 0) {
+    double m = 0.0;
+    for (int j = 0; j < k; ++j) m = fmax(m, sqrt(norms[j]));
+    s_sh = m;
+    if (blockIdx.x == 0) *scale = m;
+  }
+  __syncthreads();
+  const double s = s_sh;
+  Acc<RB, NAB> acc;
+  acc.zero();
+  double nacc = 0.0;
+  for (int64_t t = blockIdx.x; t < pl.ntiles; t += gridDim.x) {
+    const TileRange tr = tile_range(pl, t);
+    for (int e = tid; e < tr.ne; e += kBlock) {
+      const float v = static_cast<float>(R64[tr.base + e] / s);
+      R32[tr.base + e] = v;
+      P32[tr.base + e] = v;
+      D32[tr.base + e] = 0.0f;
+      Rs[e] = v;
+    }
+    __syncthreads();
+    if (pl.fused) product_tile<float, RB, NAB>(acc, Rs, Rs, tr.rows, pl, tid, 0, pl.EB);
+    norms_tile<float>(nacc, Rs, tr.rows, k, tid);
+    __syncthreads();
+  }
+  double* prow = part + (int64_t)blockIdx.x * pl.W;
+  if (pl.fused) product_finish<RB, NAB>(acc, prow, pl, scratch, tid, 0, pl.EB);
+  norms_finish(nacc, prow + pl.E, k, scratch, tid);
+}
+
+// Q = A P and the partial alpha = <<P, Q>>.
+template <typename T, int RB, int NAB>
+__global__ __launch_bounds__(kBlock) void k_spmm_product(Plan pl, const int32_t* __restrict__ rowptr,
+                                                         const int32_t* __restrict__ colind,
+                                                         const T* __restrict__ vals, const T* __restrict__ P,
+                                                         T* __restrict__ Q, double* __restrict__ part,
+                                                         const DevState* st) {
+  if (stopped(st)) return;
+  __shared__ T Ps[kTileElems];
+  __shared__ T Qs[kTileElems];
+  __shared__ double scratch[kBlock * RB * RB];
+  const int tid = threadIdx.x, k = pl.k;
+  Acc<RB, NAB> acc;
+  acc.zero();
+  for (int64_t t = blockIdx.x; t < pl.ntiles; t += gridDim.x) {
+    const TileRange tr = tile_range(pl, t);
+    for (int e = tid; e < tr.ne; e += kBlock) {
+      const int r = e / k, c = e - r * k;
+      const int64_t i = tr.row0 + r;
+      T s = T(0);
+      const int j1 = rowptr[i + 1];
+      for (int j = rowptr[i]; j < j1; ++j) s = fma(vals[j], P[(int64_t)colind[j] * k + c], s);
+      Q[tr.base + e] = s;
+      Qs[e] = s;
+      Ps[e] = P[tr.base + e];
+    }
+    __syncthreads();
+    if (pl.fused) product_tile<T, RB, NAB>(acc, Ps, Qs, tr.rows, pl, tid, 0, pl.EB);
+    __syncthreads();
+  }
+  if (pl.fused) product_finish<RB, NAB>(acc, part + (int64_t)blockIdx.x * pl.W, pl, scratch, tid, 0, pl.EB);
+}
+
+// X += P lambda, R -= Q lambda; partial <<R, R>> and column norms of R.
+template <typename T, int RB, int NAB>
+__global__ __launch_bounds__(kBlock) void k_update_xr(Plan pl, T* __restrict__ X, T* __restrict__ R,
+                                                      const T* __restrict__ P, const T* __restrict__ Q,
+                                                      const T* __restrict__ lam, double* __restrict__ part,
+                                                      const DevState* st) {
+  if (stopped(st)) return;
+  __shared__ T Ps[kTileElems];
+  __shared__ T Qs[kTileElems];
+  __shared__ T Rs[kTileElems];
+  __shared__ T lamS[kLamLds];
+  __shared__ double scratch[kBlock * RB * RB];
+  const int tid = threadIdx.x, k = pl.k, p = pl.p;
+  const bool lds_lam = pl.E <= kLamLds;
+  if (lds_lam)
+    for (int e = tid; e < pl.E; e += kBlock) lamS[e] = lam[e];
+  const T* L = lds_lam ? lamS : lam;
+  Acc<RB, NAB> acc;
+  acc.zero();
+  double nacc = 0.0;
+  for (int64_t t = blockIdx.x; t < pl.ntiles; t += gridDim.x) {
+    const TileRange tr = tile_range(pl, t);
+    for (int e = tid; e < tr.ne; e += kBlock) {
+      Ps[e] = P[tr.base + e];
+      Qs[e] = Q[tr.base + e];
+    }
+    __syncthreads();
+    for (int e = tid; e < tr.ne; e += kBlock) {
+      const int r = e / k, c = e - r * k;
+      const int g = c / p, b = c - g * p;
+      const T* lg = L + (pl.global ? 0 : g * p * p) + b;
+      const T* pr = Ps + r * k + g * p;
+      const T* qr = Qs + r * k + g * p;
+      T dx = T(0), dr = T(0);
+      for (int a = 0; a < p; ++a) {
+        const T l = lg[a * p];
+        dx = fma(pr[a], l, dx);
+        dr = fma(qr[a], l, dr);
+      }
+      X[tr.base + e] += dx;
+      const T rn = R[tr.base + e] - dr;
+      R[tr.base + e] = rn;
+      Rs[e] = rn;
+    }
+    __syncthreads();
+    if (pl.fused) product_tile<T, RB, NAB>(acc, Rs, Rs, tr.rows, pl, tid, 0, pl.EB);
+    norms_tile<T>(nacc, Rs, tr.rows, k, tid);
+    __syncthreads();
+  }
+  double* prow = part + (int64_t)blockIdx.x * pl.W;
+  if (pl.fused) product_finish<RB, NAB>(acc, prow, pl, scratch, tid, 0, pl.EB);
+  norms_finish(nacc, prow + pl.E, k, scratch, tid);
+}
+
+// P = R + P beta; partial rho = <<P, R>> for the next iteration's line 6.
+template <typename T, int RB, int NAB>
+__global__ __launch_bounds__(kBlock) void k_update_p(Plan pl, T* __restrict__ P, const T* __restrict__ R,
+                                                     const T* __restrict__ beta, double* __restrict__ part,
+                                                     const DevState* st) {
+  if (stopped(st)) return;
+  __shared__ T Ps[kTileElems];
+  __shared__ T Rs[kTileElems];
+  __shared__ T Pn[kTileElems];
+  __shared__ T betaS[kLamLds];
+  __shared__ double scratch[kBlock * RB * RB];
+  const int tid = threadIdx.x, k = pl.k, p = pl.p;
+  const bool lds_beta = pl.E <= kLamLds;
+  if (lds_beta)
+    for (int e = tid; e < pl.E; e += kBlock) betaS[e] = beta[e];
+  const T* L = lds_beta ? betaS : beta;
+  Acc<RB, NAB> acc;
+  acc.zero();
+  for (int64_t t = blockIdx.x; t < pl.ntiles; t += gridDim.x) {
+    const TileRange tr = tile_range(pl, t);
+    for (int e = tid; e < tr.ne; e += kBlock) {
+      Ps[e] = P[tr.base + e];
+      Rs[e] = R[tr.base + e];
+    }
+    __syncthreads();
+    for (int e = tid; e < tr.ne; e += kBlock) {
+      const int r = e / k, c = e - r * k;
+      const int g = c / p, b = c - g * p;
+      const T* lg = L + (pl.global ? 0 : g * p * p) + b;
+      const T* pr = Ps + r * k + g * p;
+      T dp = T(0);
+      for (int a = 0; a < p; ++a) dp = fma(pr[a], lg[a * p], dp);
+      const T pn = Rs[e] + dp;
+      P[tr.base + e] = pn;
+      Pn[e] = pn;
+    }
+    __syncthreads();
+    if (pl.fused) product_tile<T, RB, NAB>(acc, Pn, Rs, tr.rows, pl, tid, 0, pl.EB);
+    __syncthreads();
+  }
+  if (pl.fused) product_finish<RB, NAB>(acc, part + (int64_t)blockIdx.x * pl.W, pl, scratch, tid, 0, pl.EB);
+}
+
+// Stand-alone product of global X, Y for entry blocks [eb_off, eb_off + NAB*kBlock).
+template <typename T, int RB, int NAB>
+__global__ __launch_bounds__(kBlock) void k_product(Plan pl, const T* __restrict__ X, const T* __restrict__ Y,
+                                                    double* __restrict__ part, const DevState* st, int eb_off) {
+  if (stopped(st)) return;
+  __shared__ T Xs[kTileElems];
+  __shared__ T Ys[kTileElems];
+  __shared__ double scratch[kBlock * RB * RB];
+  const int tid = threadIdx.x;
+  const int eb_lim = min(pl.EB, eb_off + NAB * kBlock);
+  Acc<RB, NAB> acc;
+  acc.zero();
+  for (int64_t t = blockIdx.x; t < pl.ntiles; t += gridDim.x) {
+    const TileRange tr = tile_range(pl, t);
+    for (int e = tid; e < tr.ne; e += kBlock) {
+      Xs[e] = X[tr.base + e];
+      Ys[e] = Y[tr.base + e];
+    }
+    __syncthreads();
+    product_tile<T, RB, NAB>(acc, Xs, Ys, tr.rows, pl, tid, eb_off, eb_lim);
+    __syncthreads();
+  }
+  product_finish<RB, NAB>(acc, part + (int64_t)blockIdx.x * pl.W, pl, scratch, tid, eb_off, eb_lim);
+}
+
+// ------------------------------------------------------------------------
+// Reductions and small solves
+// ------------------------------------------------------------------------
+
+// out[e] = sum over workgroups w (fixed order) of part[w][e], e < width.
+__global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ part, double* __restrict__ out,
+                                                   int width, int W, int nwg, const DevState* st) {
+  if (stopped(st)) return;
+  __shared__ double sh[4][64];
+  const int tid = threadIdx.x, lane = tid & 63, s = tid >> 6;
+  const int e = blockIdx.x * 64 + lane;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (e < width) {
+    int w = s;
+    for (; w + 12 < nwg; w += 16) {
+      a0 += part[(int64_t)w * W + e];
+      a1 += part[(int64_t)(w + 4) * W + e];
+      a2 += part[(int64_t)(w + 8) * W + e];
+      a3 += part[(int64_t)(w + 12) * W + e];
+    }
+    for (; w < nwg; w += 4) a0 += part[(int64_t)w * W + e];
+  }
+  sh[s][lane] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  if (s == 0 && e < width) out[e] = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+}
+
+constexpr int kSmallLdsP = 48;  // p x p solves of up to this size run in LDS
+
+// lambda_g = sym(alpha_g)^{-1} rho_g by Cholesky (Algorithm 1 line 7).
+__global__ __launch_bounds__(kBlock) void k_solve_lambda(Plan pl, const double* __restrict__ alpha,
+                                                         const double* __restrict__ rho, double* __restrict__ lam,
+                                                         float* __restrict__ lam32, double* __restrict__ ws,
+                                                         DevState* st) {
+  if (stopped(st)) return;
+  const int tid = threadIdx.x, p = pl.p;
+  __shared__ int flag;
+  if (p == 1) {
+    if (tid == 0) flag = 0;
+    __syncthreads();
+    for (int e = tid; e < pl.E; e += kBlock) {
+      const double a = alpha[e], r = rho[e];
+      double l = 0.0;
+      if (pl.dec && a == 0.0 && r == 0.0) {
+        l = 0.0;
+      } else if (!(a > 0.0) || !isfinite(a)) {
+        flag = 1;
+      } else {
+        l = r / a;
+      }
+      lam[e] = l;
+      lam32[e] = static_cast<float>(l);
+    }
+    __syncthreads();
+    if (tid == 0 && flag) set_status(st, BCG_EBREAKDOWN);
+    return;
+  }
+  __shared__ double lds[2 * kSmallLdsP * kSmallLdsP];
+  const int g = blockIdx.x, pp = p * p;
+  double* M = (p <= kSmallLdsP) ? lds : ws + (int64_t)g * 2 * pp;
+  double* Y = M + pp;
+  const double* al = alpha + (int64_t)g * pp;
+  const double* rh = rho + (int64_t)g * pp;
+  if (tid == 0) flag = 0;
+  __syncthreads();
+  for (int e = tid; e < pp; e += kBlock) {
+    const int i = e / p, j = e - i * p;
+    const double m = 0.5 * (al[i * p + j] + al[j * p + i]);
+    M[e] = m;
+    Y[e] = rh[e];
+    if (!isfinite(m) || !isfinite(rh[e])) flag = 1;
+  }
+  __syncthreads();
+  // Cholesky, column by column; L overwrites the lower triangle of M.
+  for (int j = 0; j < p && !flag; ++j) {
+    if (tid == 0) {
+      const double ajj = M[j * p + j];
+      double s = 0.0;
+      for (int m = 0; m < j; ++m) s = fma(M[j * p + m], M[j * p + m], s);
+      const double d = ajj - s;
+      if (!isfinite(d) || !(d > p * DBL_EPSILON * ajj) || !(ajj > 0.0))
+        flag = 1;
+      else
+        M[j * p + j] = sqrt(d);
+    }
+    __syncthreads();
+    if (flag) break;
+    const double ljj = M[j * p + j];
+    for (int i = j + 1 + tid; i < p; i += kBlock) {
+      double s = 0.0;
+      for (int m = 0; m < j; ++m) s = fma(M[i * p + m], M[j * p + m], s);
+      M[i * p + j] = (M[i * p + j] - s) / ljj;
+    }
+    __syncthreads();
+  }
+  if (flag) {
+    if (tid == 0) set_status(st, BCG_EBREAKDOWN);
+    return;
+  }
+  for (int c = tid; c < p; c += kBlock) {
+    for (int i = 0; i < p; ++i) {  // L y = rho
+      double s = Y[i * p + c];
+      for (int m = 0; m < i; ++m) s -= M[i * p + m] * Y[m * p + c];
+      Y[i * p + c] = s / M[i * p + i];
+    }
+    for (int i = p - 1; i >= 0; --i) {  // L^T x = y
+      double s = Y[i * p + c];
+      for (int m = i + 1; m < p; ++m) s -= M[m * p + i] * Y[m * p + c];
+      Y[i * p + c] = s / M[i * p + i];
+    }
+  }
+  __syncthreads();
+  double* lo = lam + (int64_t)g * pp;
+  float* lo32 = lam32 + (int64_t)g * pp;
+  for (int e = tid; e < pp; e += kBlock) {
+    lo[e] = Y[e];
+    lo32[e] = static_cast<float>(Y[e]);
+  }
+}
+
+// Stop rule (Section 4 reading: every column's recursive residual norm below
+// tol times its initial norm), then beta_g = rho_g^{-1} rho_new_g by LU with
+// partial pivoting (Algorithm 1 lines 9-12).
+__global__ __launch_bounds__(kBlock) void k_conv_beta(Plan pl, const double* __restrict__ red_new,
+                                                      const double* __restrict__ r0,
+                                                      const double* __restrict__ rho_old, double* __restrict__ beta,
+                                                      float* __restrict__ beta32, double* __restrict__ ws,
+                                                      double* __restrict__ ratios, DevState* st, double tol, int it,
+                                                      int maxit) {
+  if (stopped(st)) return;
+  const int tid = threadIdx.x, k = pl.k, p = pl.p;
+  __shared__ double smax[kBlock];
+  __shared__ int sbad[kBlock];
+  __shared__ int flag;
+  double m = 0.0;
+  int bad = 0;
+  for (int j = tid; j < k; j += kBlock) {
+    const double c = red_new[pl.E + j];
+    const double rr = r0[j];
+    const double ratio = (rr == 0.0) ? 0.0 : sqrt(c) / rr;
+    if (!isfinite(ratio))
+      bad = 1;
+    else
+      m = fmax(m, ratio);
+    if (blockIdx.x == 0) ratios[j] = ratio;
+  }
+  smax[tid] = m;
+  sbad[tid] = bad;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      smax[tid] = fmax(smax[tid], smax[tid + s]);
+      sbad[tid] |= sbad[tid + s];
+    }
+    __syncthreads();
+  }
+  const bool lead = blockIdx.x == 0 && tid == 0;
+  if (lead) {
+    st->iter = it;
+    st->max_ratio = sbad[0] ? NAN : smax[0];
+  }
+  if (sbad[0]) {
+    if (lead) set_status(st, BCG_EBREAKDOWN);
+    return;
+  }
+  if (smax[0] <= tol) {
+    if (lead) set_status(st, BCG_OK);
+    return;
+  }
+  if (it >= maxit) {
+    if (lead) set_status(st, BCG_NOT_CONVERGED);
+    return;
+  }
+  if (tid == 0) flag = 0;
+  __syncthreads();
+  if (p == 1) {
+    for (int e = tid; e < pl.E; e += kBlock) {
+      const double r = rho_old[e];
+      double b = 0.0;
+      if (pl.dec && r == 0.0) {
+        b = 0.0;
+      } else if (r == 0.0 || !isfinite(r)) {
+        flag = 1;
+      } else {
+        b = red_new[e] / r;
+      }
+      beta[e] = b;
+      beta32[e] = static_cast<float>(b);
+    }
+    __syncthreads();
+    if (tid == 0 && flag) set_status(st, BCG_EBREAKDOWN);
+    return;
+  }
+  __shared__ double lds[2 * kSmallLdsP * kSmallLdsP];
+  __shared__ int piv;
+  const int g = blockIdx.x, pp = p * p;
+  double* M = (p <= kSmallLdsP) ? lds : ws + (int64_t)g * 2 * pp;
+  double* Y = M + pp;
+  for (int e = tid; e < pp; e += kBlock) {
+    M[e] = rho_old[(int64_t)g * pp + e];
+    Y[e] = red_new[(int64_t)g * pp + e];
+    if (!isfinite(M[e])) flag = 1;
+  }
+  __syncthreads();
+  for (int j = 0; j < p && !flag; ++j) {
+    if (tid == 0) {
+      int best_i = j;
+      double best = fabs(M[j * p + j]);
+      for (int i = j + 1; i < p; ++i) {
+        const double v = fabs(M[i * p + j]);
+        if (v > best) {
+          best = v;
+          best_i = i;
+        }
+      }
+      if (best == 0.0) flag = 1;
+      piv = best_i;
+    }
+    __syncthreads();
+    if (flag) break;
+    const int pr = piv;
+    if (pr != j) {
+      for (int c = tid; c < p; c += kBlock) {
+        double t = M[j * p + c];
+        M[j * p + c] = M[pr * p + c];
+        M[pr * p + c] = t;
+        t = Y[j * p + c];
+        Y[j * p + c] = Y[pr * p + c];
+        Y[pr * p + c] = t;
+      }
+      __syncthreads();
+    }
+    const double djj = M[j * p + j];
+    const int rows = p - 1 - j;
+    // eliminate below the pivot: columns j+1.. of M and all columns of Y
+    for (int e = tid; e < rows * (2 * p); e += kBlock) {
+      const int i = j + 1 + e / (2 * p);
+      const int c = e % (2 * p);
+      const double l = M[i * p + j] / djj;
+      if (c < p) {
+        if (c > j) M[i * p + c] -= l * M[j * p + c];
+      } else {
+        Y[i * p + (c - p)] -= l * Y[j * p + (c - p)];
+      }
+    }
+    __syncthreads();
+  }
+  if (flag) {
+    if (tid == 0) set_status(st, BCG_EBREAKDOWN);
+    return;
+  }
+  for (int c = tid; c < p; c += kBlock) {
+    for (int i = p - 1; i >= 0; --i) {
+      double s = Y[i * p + c];
+      for (int m2 = i + 1; m2 < p; ++m2) s -= M[i * p + m2] * Y[m2 * p + c];
+      Y[i * p + c] = s / M[i * p + i];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < pp; e += kBlock) {
+    beta[(int64_t)g * pp + e] = Y[e];
+    beta32[(int64_t)g * pp + e] = static_cast<float>(Y[e]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_axpy_scaled(int64_t count, double* __restrict__ X,
+                                                        const float* __restrict__ D, const double* __restrict__ scale) {
+  const double s = *scale;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < count; e += (int64_t)gridDim.x * kBlock)
+    X[e] += s * static_cast<double>(D[e]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cast_values(int64_t nnz, const double* __restrict__ v,
+                                                        float* __restrict__ v32) {
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kBlock)
+    v32[e] = static_cast<float>(v[e]);
+}
+
+// out[e] = alpha * <Y[row(e), :], X[col(e), :]>; L lanes per row.
+__global__ __launch_bounds__(kBlock) void k_sampled_outer(int64_t n, int k, int L, const int32_t* __restrict__ rowptr,
+                                                          const int32_t* __restrict__ colind,
+                                                          const double* __restrict__ Y, const double* __restrict__ X,
+                                                          double alpha, double* __restrict__ out) {
+  const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t row = gt / L;
+  const int lane = static_cast<int>(gt % L);
+  if (row >= n) return;  // whole L-lane groups leave together (L divides 64)
+  const double* yr = Y + row * k;
+  const int j1 = rowptr[row + 1];
+  for (int j = rowptr[row]; j < j1; ++j) {
+    const double* xr = X + (int64_t)colind[j] * k;
+    double s = 0.0;
+    for (int c = lane; c < k; c += L) s = fma(yr[c], xr[c], s);
+    for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
+    if (lane == 0) out[j] = alpha * s;
+  }
+}
+
+// ------------------------------------------------------------------------
+// Template dispatch on the accumulation shape
+// ------------------------------------------------------------------------
+template <typename F>
+void dispatch_shape(const Plan& pl, F&& f) {
+  if (pl.rb == 2) {
+    if (pl.EB <= kBlock)
+      f(std::integral_constant<int, 2>(), std::integral_constant<int, 1>());
+    else
+      f(std::integral_constant<int, 2>(), std::integral_constant<int, kNabMax>());
+  } else {
+    if (pl.EB <= kBlock)
+      f(std::integral_constant<int, 1>(), std::integral_constant<int, 1>());
+    else
+      f(std::integral_constant<int, 1>(), std::integral_constant<int, kNabMax>());
+  }
+}
+
+}  // namespace
+
+Plan make_plan(int64_t n, int k, int p, int global, int dec) {
+  Plan pl{};
+  pl.n = n;
+  pl.k = k;
+  pl.p = p;
+  pl.q = k / p;
+  pl.global = global;
+  pl.dec = dec;
+  pl.qo = global ? 1 : pl.q;
+  pl.E = pl.qo * p * p;
+  pl.W = pl.E + k;
+  pl.rb = (p % 2 == 0) ? 2 : 1;
+  pl.pb = p / pl.rb;
+  pl.EB = pl.qo * pl.pb * pl.pb;
+  if (pl.EB <= kBlock) {
+    pl.S = kBlock / pl.EB;
+    pl.nab = 1;
+  } else {
+    pl.S = 1;
+    pl.nab = (pl.EB + kBlock - 1) / kBlock;
+  }
+  pl.fused = pl.nab <= kNabMax;
+  pl.TR = kTileElems / k > 0 ? kTileElems / k : 1;
+  pl.ntiles = (n + pl.TR - 1) / pl.TR;
+  pl.nwg = static_cast<int>(pl.ntiles < kMaxWG ? pl.ntiles : kMaxWG);
+  if (pl.nwg < 1) pl.nwg = 1;
+  return pl;
+}
+
+void launch_residual(const Plan& pl, const int32_t* rowptr, const int32_t* colind, const double* vals,
+                     const double* B, const double* X, double* R, double* P, double* part, int with_p,
+                     hipStream_t s) {
+  dispatch_shape(pl, [&](auto RB, auto NAB) {
+    hipLaunchKernelGGL((k_residual<decltype(RB)::value, decltype(NAB)::value>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, rowptr, colind, vals, B, X,
+                       R, P, part, with_p);
+  });
+}
+
+void launch_cast_init(const Plan& pl, const double* R64, const double* norms, float* R32, float* P32, float* D32,
+                      double* scale, double* part, hipStream_t s) {
+  dispatch_shape(pl, [&](auto RB, auto NAB) {
+    hipLaunchKernelGGL((k_cast_init<decltype(RB)::value, decltype(NAB)::value>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, R64, norms, R32, P32, D32,
+                       scale, part);
+  });
+}
+
+template <typename T>
+void launch_spmm_product(const Plan& pl, const int32_t* rowptr, const int32_t* colind, const T* vals, const T* P,
+                         T* Q, double* part, const DevState* st, hipStream_t s) {
+  dispatch_shape(pl, [&](auto RB, auto NAB) {
+    hipLaunchKernelGGL((k_spmm_product<T, decltype(RB)::value, decltype(NAB)::value>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, rowptr, colind, vals,
+                       P, Q, part, st);
+  });
+}
+
+template <typename T>
+void launch_update_xr(const Plan& pl, T* X, T* R, const T* P, const T* Q, const T* lam, double* part,
+                      const DevState* st, hipStream_t s) {
+  dispatch_shape(pl, [&](auto RB, auto NAB) {
+    hipLaunchKernelGGL((k_update_xr<T, decltype(RB)::value, decltype(NAB)::value>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, X, R, P, Q, lam, part,
+                       st);
+  });
+}
+
+template <typename T>
+void launch_update_p(const Plan& pl, T* P, const T* R, const T* beta, double* part, const DevState* st,
+                     hipStream_t s) {
+  dispatch_shape(pl, [&](auto RB, auto NAB) {
+    hipLaunchKernelGGL((k_update_p<T, decltype(RB)::value, decltype(NAB)::value>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, P, R, beta, part, st);
+  });
+}
+
+template <typename T>
+void launch_product(const Plan& pl, const T* X, const T* Y, double* part, const DevState* st, hipStream_t s) {
+  const int chunk = kNabMax * kBlock;
+  for (int off = 0; off < pl.EB; off += chunk) {
+    if (pl.rb == 2)
+      hipLaunchKernelGGL((k_product<T, 2, kNabMax>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, X, Y, part, st, off);
+    else
+      hipLaunchKernelGGL((k_product<T, 1, kNabMax>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, X, Y, part, st, off);
+  }
+}
+
+void launch_reduce(const Plan& pl, const double* part, double* out, int width, const DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3((width + 63) / 64), dim3(kBlock), 0, s, part, out, width, pl.W, pl.nwg, st);
+}
+
+void launch_solve_lambda(const Plan& pl, const double* alpha, const double* rho, double* lam, float* lam32,
+                         double* ws, DevState* st, hipStream_t s) {
+  const int grid = pl.p == 1 ? 1 : pl.qo;
+  hipLaunchKernelGGL(k_solve_lambda, dim3(grid), dim3(kBlock), 0, s, pl, alpha, rho, lam, lam32, ws, st);
+}
+
+void launch_conv_beta(const Plan& pl, const double* red_new, const double* r0, const double* rho_old, double* beta,
+                      float* beta32, double* ws, double* ratios, DevState* st, double tol, int it, int maxit,
+                      hipStream_t s) {
+  const int grid = pl.p == 1 ? 1 : pl.qo;
+  hipLaunchKernelGGL(k_conv_beta, dim3(grid), dim3(kBlock), 0, s, pl, red_new, r0, rho_old, beta, beta32, ws, ratios,
+                     st, tol, it, maxit);
+}
+
+void launch_axpy_scaled(int64_t count, double* X, const float* D, const double* scale, hipStream_t s) {
+  const int64_t blocks = (count + kBlock - 1) / kBlock;
+  const int grid = static_cast<int>(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096);
+  hipLaunchKernelGGL(k_axpy_scaled, dim3(grid), dim3(kBlock), 0, s, count, X, D, scale);
+}
+
+void launch_cast_values(int64_t nnz, const double* v, float* v32, hipStream_t s) {
+  const int64_t blocks = (nnz + kBlock - 1) / kBlock;
+  const int grid = static_cast<int>(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096);
+  hipLaunchKernelGGL(k_cast_values, dim3(grid), dim3(kBlock), 0, s, nnz, v, v32);
+}
+
+void launch_sampled_outer(int64_t n, int k, const int32_t* rowptr, const int32_t* colind, const double* Y,
+                          const double* X, double alpha, double* out, hipStream_t s) {
+  int L = 1;
+  while (L * 2 <= k && L * 2 <= 64) L *= 2;
+  const int64_t threads = n * L;
+  const int64_t grid = (threads + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_sampled_outer, dim3(static_cast<unsigned>(grid)), dim3(kBlock), 0, s, n, k, L, rowptr, colind,
+                     Y, X, alpha, out);
+}
+
+template void launch_spmm_product<double>(const Plan&, const int32_t*, const int32_t*, const double*, const double*,
+                                          double*, double*, const DevState*, hipStream_t);
+template void launch_spmm_product<float>(const Plan&, const int32_t*, const int32_t*, const float*, const float*,
+                                         float*, double*, const DevState*, hipStream_t);
+template void launch_update_xr<double>(const Plan&, double*, double*, const double*, const double*, const double*,
+                                       double*, const DevState*, hipStream_t);
+template void launch_update_xr<float>(const Plan&, float*, float*, const float*, const float*, const float*, double*,
+                                      const DevState*, hipStream_t);
+template void launch_update_p<double>(const Plan&, double*, const double*, const double*, double*, const DevState*,
+                                      hipStream_t);
+template void launch_update_p<float>(const Plan&, float*, const float*, const float*, double*, const DevState*,
+                                     hipStream_t);
+template void launch_product<double>(const Plan&, const double*, const double*, double*, const DevState*,
+                                     hipStream_t);
+template void launch_product<float>(const Plan&, const float*, const float*, double*, const DevState*, hipStream_t);
+
+}  // namespace bcg

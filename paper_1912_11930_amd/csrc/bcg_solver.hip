@@ -1,0 +1,651 @@
+// Solver runtime behind the C ABI: handle, workspace, the iteration driver of
+// Algorithm 1 (Section 3, M = I) and the FP32/FP64 refinement loop.
+//
+// The host enqueues iterations in chunks and never waits inside a chunk: the
+// kernels of every iteration return at entry once the device-side `done`
+// flag is set (converged, breakdown or iteration cap), so the stop iteration
+// is exactly the one the stop rule accepted. The host keeps two chunks in
+// flight and reads the flag of the older one through pinned memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bcg.h"
+#include "bcg_internal.h"
+
+using namespace bcg;
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(BCG_EHIP, "%s: %s", #expr, hipGetErrorString(e_));    \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+template <typename T>
+int dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(BCG_ENOMEM, "device allocation of %zu bytes failed", count * sizeof(T));
+  }
+  return BCG_OK;
+}
+
+// Buffers of one precision's iteration: block vectors and coefficients.
+template <typename T>
+struct IterBuffers {
+  const T* vals;
+  T *X, *R, *P, *Q;
+  const T *lam, *beta;
+};
+
+}  // namespace
+
+struct bcg_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t n = 0, nnz = 0;
+  int k = 0, p = 0, variant = 0;
+  Plan pl{};
+  int32_t *rowptr = nullptr, *colind = nullptr;
+  double* vals = nullptr;
+  float* vals32 = nullptr;
+  double *R = nullptr, *P = nullptr, *Q = nullptr;
+  double *partA = nullptr, *partR = nullptr, *partN = nullptr;
+  double *alpha = nullptr, *rho = nullptr, *rnew = nullptr;
+  double *lam = nullptr, *beta = nullptr, *ws = nullptr;
+  float *lam32 = nullptr, *beta32 = nullptr;
+  double *r0 = nullptr, *ratios = nullptr, *scale = nullptr;
+  DevState* st = nullptr;
+  DevState* st_host = nullptr;  // pinned, 2 slots
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  // refinement mode
+  int precision = BCG_FP64;
+  double inner_tol = 1e-4;
+  int inner_maxit = 1000, max_outer = 50;
+  float *R32 = nullptr, *P32 = nullptr, *Q32 = nullptr, *D32 = nullptr;
+  int chunk = 32;       // upper bound on iterations enqueued per poll
+  // per-kernel-class event timing
+  struct ProfRec {
+    int cls, it;
+    hipEvent_t a, b;
+  };
+  bool prof_on = false;
+  unsigned prof_mask = 0;  // classes bracketed by events
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<ProfRec> prof_recs;
+  bcg_kernel_time prof[BCG_NUM_KERNEL_CLASSES]{};
+  std::vector<double> ref_r0;  // host copy of the stop rule's reference norms
+  bcg_info info{};
+  std::vector<double> host_ratios;
+};
+
+namespace {
+
+void free_all(bcg_handle* h) {
+  void* ptrs[] = {h->rowptr, h->colind, h->vals, h->vals32, h->R, h->P, h->Q, h->partA, h->partR, h->partN,
+                  h->alpha, h->rho, h->rnew, h->lam, h->beta, h->ws, h->lam32, h->beta32, h->r0, h->ratios,
+                  h->scale, h->st, h->R32, h->P32, h->Q32, h->D32};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (h->st_host) (void)hipHostFree(h->st_host);
+  for (auto& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& r : h->prof_recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto& e : h->ev_pool) (void)hipEventDestroy(e);
+}
+
+hipEvent_t pool_event(bcg_handle* h) {
+  if (!h->ev_pool.empty()) {
+    hipEvent_t e = h->ev_pool.back();
+    h->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// Launches `f` (one kernel class), bracketed by events when profiling.
+template <typename F>
+void timed(bcg_handle* h, int cls, int it, F&& f) {
+  if (!h->prof_on || !((h->prof_mask >> cls) & 1u)) {
+    f();
+    return;
+  }
+  hipEvent_t a = pool_event(h), b = pool_event(h);
+  (void)hipEventRecord(a, h->stream);
+  f();
+  (void)hipEventRecord(b, h->stream);
+  h->prof_recs.push_back({cls, it, a, b});
+}
+
+// Accumulates the recorded launches of iterations <= last_it (0 = set-up
+// launches); the others returned at entry and are dropped. Stream must be idle.
+void prof_collect(bcg_handle* h, int last_it) {
+  for (auto& r : h->prof_recs) {
+    if (r.it <= last_it) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+        h->prof[r.cls].launches += 1;
+        h->prof[r.cls].total_ms += ms;
+      }
+    }
+    h->ev_pool.push_back(r.a);
+    h->ev_pool.push_back(r.b);
+  }
+  h->prof_recs.clear();
+}
+
+int alloc_fp32(bcg_handle* h) {
+  if (h->R32) return BCG_OK;
+  const size_t nk = static_cast<size_t>(h->n) * h->k;
+  int rc;
+  if ((rc = dalloc(&h->R32, nk)) || (rc = dalloc(&h->P32, nk)) || (rc = dalloc(&h->Q32, nk)) ||
+      (rc = dalloc(&h->D32, nk)))
+    return rc;
+  return BCG_OK;
+}
+
+int reset_state(bcg_handle* h) {
+  DevState z{};
+  HIP_TRY(hipMemcpyAsync(h->st, &z, sizeof z, hipMemcpyHostToDevice, h->stream));
+  return BCG_OK;
+}
+
+int read_state(bcg_handle* h, DevState* out) {
+  HIP_TRY(hipMemcpyAsync(h->st_host, h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  *out = h->st_host[0];
+  return BCG_OK;
+}
+
+// Norms^2 of the k columns (the tail of a reduced partial row) to the host.
+int fetch_norms(bcg_handle* h, const double* red, std::vector<double>& out) {
+  out.resize(h->k);
+  HIP_TRY(hipMemcpyAsync(out.data(), red + h->pl.E, sizeof(double) * h->k, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return BCG_OK;
+}
+
+bool decoupled(const bcg_handle* h) { return h->p == 1 && (h->variant == BCG_PARALLEL || h->variant == BCG_HYBRID); }
+
+// Enqueues one iteration (number `it`) of Algorithm 1 in precision T.
+template <typename T>
+void enqueue_iteration(bcg_handle* h, const IterBuffers<T>& b, double tol, int it, int maxit) {
+  const Plan& pl = h->pl;
+  hipStream_t s = h->stream;
+  timed(h, BCG_K_SPMM, it, [&] {  // lines 4-5
+    launch_spmm_product<T>(pl, h->rowptr, h->colind, b.vals, b.P, b.Q, h->partA, h->st, s);
+  });
+  if (!pl.fused) timed(h, BCG_K_PRODUCT, it, [&] { launch_product<T>(pl, b.P, b.Q, h->partA, h->st, s); });
+  timed(h, BCG_K_REDUCE, it, [&] { launch_reduce(pl, h->partA, h->alpha, pl.E, h->st, s); });
+  timed(h, BCG_K_SMALL, it, [&] {  // line 7
+    launch_solve_lambda(pl, h->alpha, h->rho, h->lam, h->lam32, h->ws, h->st, s);
+  });
+  timed(h, BCG_K_UPDATE_XR, it, [&] {  // lines 8-9 and the product of line 11
+    launch_update_xr<T>(pl, b.X, b.R, b.P, b.Q, b.lam, h->partN, h->st, s);
+  });
+  if (!pl.fused) timed(h, BCG_K_PRODUCT, it, [&] { launch_product<T>(pl, b.R, b.R, h->partN, h->st, s); });
+  timed(h, BCG_K_REDUCE, it, [&] { launch_reduce(pl, h->partN, h->rnew, pl.W, h->st, s); });
+  timed(h, BCG_K_SMALL, it, [&] {  // stop rule, line 12
+    launch_conv_beta(pl, h->rnew, h->r0, h->rho, h->beta, h->beta32, h->ws, h->ratios, h->st, tol, it, maxit, s);
+  });
+  // line 13 and the recomputed rho of line 6 for the next iteration; after
+  // the last iteration these launches return at entry
+  timed(h, BCG_K_UPDATE_P, it + 1, [&] { launch_update_p<T>(pl, b.P, b.R, b.beta, h->partR, h->st, s); });
+  if (!pl.fused) timed(h, BCG_K_PRODUCT, it + 1, [&] { launch_product<T>(pl, b.P, b.R, h->partR, h->st, s); });
+  timed(h, BCG_K_REDUCE, it + 1, [&] { launch_reduce(pl, h->partR, h->rho, pl.E, h->st, s); });
+}
+
+// Iterations to enqueue next: half the predicted remaining count (from the
+// observed geometric decrease of the largest ratio), at least 1, at most
+// h->chunk; keeps the launches enqueued past the stop iteration few.
+int next_chunk(const bcg_handle* h, double tol, int enq, int it_a, double r_a, int it_b, double r_b) {
+  const int cap = h->chunk;
+  if (!(tol > 0.0) || it_b <= it_a || !(r_a > 0.0) || !(r_b > 0.0) || !(r_b < r_a)) return cap;
+  const double rate = (std::log(r_b) - std::log(r_a)) / (it_b - it_a);  // < 0
+  const double remaining = (std::log(tol) - std::log(r_b)) / rate - (enq - it_b);
+  if (!(remaining < 1e9)) return cap;
+  const int c = static_cast<int>(std::ceil(0.5 * remaining));
+  return std::max(1, std::min(cap, c));
+}
+
+// Runs iterations 1..maxit until the device flags completion; rho must hold
+// the reduced <<P^1, R^0>> and r0 the reference norms.
+template <typename T>
+int run_iterations(bcg_handle* h, const IterBuffers<T>& b, double tol, int maxit, DevState* final_state) {
+  int enq = 0;
+  int slot_head = 0, inflight = 0;
+  int it_a = 0, it_b = 0;
+  double r_a = 0.0, r_b = 0.0;
+  auto enqueue_chunk = [&](int slot, int want) -> int {
+    const int c = std::min(want, maxit - enq);
+    for (int j = 0; j < c; ++j) enqueue_iteration<T>(h, b, tol, enq + 1 + j, maxit);
+    enq += c;
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(&h->st_host[slot], h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipEventRecord(h->ev[slot], h->stream));
+    return BCG_OK;
+  };
+  const int first = std::min(h->chunk, 8);
+  int rc;
+  if (maxit > 0) {
+    if ((rc = enqueue_chunk(0, first))) return rc;
+    inflight = 1;
+    if (enq < maxit) {
+      if ((rc = enqueue_chunk(1, first))) return rc;
+      inflight = 2;
+    }
+  }
+  while (inflight > 0) {
+    HIP_TRY(hipEventSynchronize(h->ev[slot_head]));
+    const DevState seen = h->st_host[slot_head];
+    --inflight;
+    const int freed = slot_head;
+    slot_head ^= 1;
+    if (seen.done) break;
+    it_a = it_b;
+    r_a = r_b;
+    it_b = seen.iter;
+    r_b = seen.max_ratio;
+    if (enq < maxit) {
+      if ((rc = enqueue_chunk(freed, next_chunk(h, tol, enq, it_a, r_a, it_b, r_b)))) return rc;
+      ++inflight;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  rc = read_state(h, final_state);
+  if (h->prof_on) prof_collect(h, final_state->iter);
+  return rc;
+}
+
+// Sets r0 (device) from host norms^2; applies the input checks of the paper's
+// reading (zero columns only in the diagonal subalgebra).
+int set_reference(bcg_handle* h, const std::vector<double>& norms2, std::vector<double>& r0, bool* all_zero,
+                  bool allow_zero) {
+  r0.resize(h->k);
+  bool any_zero = false;
+  *all_zero = true;
+  for (int j = 0; j < h->k; ++j) {
+    const double v = std::sqrt(norms2[j]);
+    if (!std::isfinite(v)) return fail(BCG_EINVAL, "non-finite initial residual in column %d", j);
+    r0[j] = v;
+    if (v == 0.0)
+      any_zero = true;
+    else
+      *all_zero = false;
+  }
+  if (any_zero && !*all_zero && !allow_zero)
+    return fail(BCG_EINVAL, "zero initial residual column with a non-diagonal subalgebra");
+  HIP_TRY(hipMemcpyAsync(h->r0, r0.data(), sizeof(double) * h->k, hipMemcpyHostToDevice, h->stream));
+  return BCG_OK;
+}
+
+double max_ratio(const std::vector<double>& norms2, const std::vector<double>& r0) {
+  double m = 0.0;
+  for (size_t j = 0; j < r0.size(); ++j) {
+    const double v = r0[j] == 0.0 ? 0.0 : std::sqrt(norms2[j]) / r0[j];
+    if (!std::isfinite(v)) return NAN;
+    m = std::max(m, v);
+  }
+  return m;
+}
+
+// Plain FP64 solve from the current X. ref_r0 (host, optional) replaces the
+// initial residual norms in the stop rule.
+int solve_fp64(bcg_handle* h, const double* B, double* X, double tol, int maxit, const std::vector<double>* ref_r0,
+               int* iterations) {
+  const Plan& pl = h->pl;
+  int rc;
+  *iterations = 0;
+  if ((rc = reset_state(h))) return rc;
+  timed(h, BCG_K_RESIDUAL, 0, [&] {  // lines 1-2
+    launch_residual(pl, h->rowptr, h->colind, h->vals, B, X, h->R, h->P, h->partR, 1, h->stream);
+  });
+  if (!pl.fused)
+    timed(h, BCG_K_PRODUCT, 0, [&] { launch_product<double>(pl, h->R, h->R, h->partR, nullptr, h->stream); });
+  timed(h, BCG_K_REDUCE, 0, [&] { launch_reduce(pl, h->partR, h->rho, pl.W, nullptr, h->stream); });
+  HIP_TRY(hipGetLastError());
+  std::vector<double> norms2, r0;
+  if ((rc = fetch_norms(h, h->rho, norms2))) return rc;
+  bool all_zero = false;
+  if (ref_r0) {
+    for (int j = 0; j < h->k; ++j)
+      if (!std::isfinite(norms2[j])) return fail(BCG_EINVAL, "non-finite residual in column %d", j);
+    r0 = *ref_r0;
+    all_zero = true;
+    for (double v : r0) all_zero &= (v == 0.0);
+    HIP_TRY(hipMemcpyAsync(h->r0, r0.data(), sizeof(double) * h->k, hipMemcpyHostToDevice, h->stream));
+  } else if ((rc = set_reference(h, norms2, r0, &all_zero, decoupled(h)))) {
+    return rc;
+  }
+  h->ref_r0 = r0;
+  for (int j = 0; j < h->k; ++j) h->host_ratios[j] = r0[j] == 0.0 ? 0.0 : std::sqrt(norms2[j]) / r0[j];
+  if (all_zero) return BCG_OK;
+  if (maxit == 0) return BCG_NOT_CONVERGED;
+  IterBuffers<double> b{h->vals, X, h->R, h->P, h->Q, h->lam, h->beta};
+  DevState fin{};
+  if ((rc = run_iterations<double>(h, b, tol, maxit, &fin))) return rc;
+  *iterations = fin.iter;
+  if (fin.iter > 0)
+    HIP_TRY(hipMemcpy(h->host_ratios.data(), h->ratios, sizeof(double) * h->k, hipMemcpyDeviceToHost));
+  if (!fin.done) return BCG_NOT_CONVERGED;
+  return fin.status;
+}
+
+// Mixed precision: FP32 inner block CG, FP64 outer iterative refinement.
+int solve_refine(bcg_handle* h, const double* B, double* X, double tol, int maxit) {
+  const Plan& pl = h->pl;
+  int rc;
+  if ((rc = alloc_fp32(h))) return rc;
+  bcg_info& info = h->info;
+  // true FP64 residual and its column norms
+  timed(h, BCG_K_RESIDUAL, 0, [&] {
+    launch_residual(pl, h->rowptr, h->colind, h->vals, B, X, h->R, nullptr, h->partN, 0, h->stream);
+  });
+  timed(h, BCG_K_REDUCE, 0, [&] { launch_reduce(pl, h->partN, h->rnew, pl.W, nullptr, h->stream); });
+  HIP_TRY(hipGetLastError());
+  std::vector<double> norms2, r0;
+  if ((rc = fetch_norms(h, h->rnew, norms2))) return rc;
+  bool all_zero = false;
+  if ((rc = set_reference(h, norms2, r0, &all_zero, decoupled(h)))) return rc;
+  h->ref_r0 = r0;
+  if (all_zero) return BCG_OK;
+  double prev = INFINITY;
+  for (int outer = 1;; ++outer) {
+    const double ratio = max_ratio(norms2, r0);
+    for (int j = 0; j < h->k; ++j) h->host_ratios[j] = r0[j] == 0.0 ? 0.0 : std::sqrt(norms2[j]) / r0[j];
+    if (!(ratio == ratio)) return fail(BCG_EBREAKDOWN, "non-finite residual during refinement");
+    if (ratio <= tol) return BCG_OK;
+    bool fallback = ratio > 0.5 * prev;
+    if (!fallback && outer > h->max_outer) return BCG_NOT_CONVERGED;
+    if (!fallback) {
+      prev = ratio;
+      // inner FP32 solve of A D = R / s from D = 0
+      if ((rc = reset_state(h))) return rc;
+      timed(h, BCG_K_RESIDUAL, 0, [&] {
+        launch_cast_init(pl, h->R, h->rnew + pl.E, h->R32, h->P32, h->D32, h->scale, h->partR, h->stream);
+      });
+      if (!pl.fused)
+        timed(h, BCG_K_PRODUCT, 0, [&] { launch_product<float>(pl, h->R32, h->R32, h->partR, nullptr, h->stream); });
+      timed(h, BCG_K_REDUCE, 0, [&] { launch_reduce(pl, h->partR, h->rho, pl.W, nullptr, h->stream); });
+      std::vector<double> in2, rin;
+      if ((rc = fetch_norms(h, h->rho, in2))) return rc;
+      bool inner_zero = false;
+      rc = set_reference(h, in2, rin, &inner_zero, decoupled(h));
+      if (rc == BCG_EINVAL) {
+        fallback = true;
+      } else if (rc) {
+        return rc;
+      } else {
+        IterBuffers<float> b{h->vals32, h->D32, h->R32, h->P32, h->Q32, h->lam32, h->beta32};
+        DevState fin{};
+        if ((rc = run_iterations<float>(h, b, h->inner_tol, h->inner_maxit, &fin))) return rc;
+        info.iterations += fin.iter;
+        info.outer_iterations = outer;
+        if (fin.status < 0) {
+          fallback = true;
+        } else {
+          timed(h, BCG_K_RESIDUAL, 0, [&] { launch_axpy_scaled(h->n * h->k, X, h->D32, h->scale, h->stream); });
+          timed(h, BCG_K_RESIDUAL, 0, [&] {
+            launch_residual(pl, h->rowptr, h->colind, h->vals, B, X, h->R, nullptr, h->partN, 0, h->stream);
+          });
+          timed(h, BCG_K_REDUCE, 0, [&] { launch_reduce(pl, h->partN, h->rnew, pl.W, nullptr, h->stream); });
+          HIP_TRY(hipGetLastError());
+          if ((rc = fetch_norms(h, h->rnew, norms2))) return rc;
+          continue;
+        }
+      }
+    }
+    // stagnation or inner breakdown: finish with the FP64 iteration from X
+    info.fp64_fallback = 1;
+    int its = 0;
+    rc = solve_fp64(h, B, X, tol, maxit, &r0, &its);
+    info.iterations += its;
+    return rc;
+  }
+}
+
+int validate_p(int variant, int k, int p, int* p_out) {
+  if (k < 1 || k > 256) return fail(BCG_EINVAL, "k=%d outside 1..256", k);
+  switch (variant) {
+    case BCG_BLOCK:
+      if (p != 0 && p != k) return fail(BCG_EINVAL, "block subalgebra needs p = k or 0 (got %d)", p);
+      *p_out = k;
+      return BCG_OK;
+    case BCG_PARALLEL:
+      if (p != 0 && p != 1) return fail(BCG_EINVAL, "parallel subalgebra needs p = 1 or 0 (got %d)", p);
+      *p_out = 1;
+      return BCG_OK;
+    case BCG_GLOBAL:
+      if (p == 0) {
+        *p_out = 1;
+        return BCG_OK;
+      }
+      [[fallthrough]];
+    case BCG_HYBRID:
+      if (p < 1 || p > k || k % p) return fail(BCG_EINVAL, "p=%d must divide k=%d", p, k);
+      *p_out = p;
+      return BCG_OK;
+    default:
+      return fail(BCG_EINVAL, "unknown subalgebra %d", variant);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bcg_last_error(void) { return g_error.c_str(); }
+
+int bcg_create(const bcg_csr* A, int k, int subalgebra, int p, bcg_handle** out) {
+  g_error.clear();
+  if (!out) return fail(BCG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!A || !A->rowptr || !A->colind || !A->values) return fail(BCG_EINVAL, "CSR arrays must be non-NULL");
+  if (A->n < 1 || A->n >= INT32_MAX || A->nnz < 0 || A->nnz >= INT32_MAX)
+    return fail(BCG_EINVAL, "n=%lld nnz=%lld outside the int32 index range", (long long)A->n, (long long)A->nnz);
+  int pn = 0;
+  int rc = validate_p(subalgebra, k, p, &pn);
+  if (rc) return rc;
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device));
+  auto* h = new bcg_handle();
+  h->device = device;
+  h->n = A->n;
+  h->nnz = A->nnz;
+  h->k = k;
+  h->p = pn;
+  h->variant = subalgebra;
+  const int dec = pn == 1 && (subalgebra == BCG_PARALLEL || subalgebra == BCG_HYBRID);
+  h->pl = make_plan(h->n, k, pn, subalgebra == BCG_GLOBAL ? 1 : 0, dec);
+  if (const char* env = std::getenv("BCG_POLL_EVERY")) h->chunk = std::max(1, std::atoi(env));
+  h->host_ratios.assign(k, 1.0);
+  const Plan& pl = h->pl;
+  const size_t nk = static_cast<size_t>(h->n) * k;
+  const size_t partsz = static_cast<size_t>(pl.nwg) * pl.W;
+  const size_t wssz = (pl.p > 48) ? static_cast<size_t>(pl.qo) * 2 * pl.p * pl.p : 1;
+  if ((rc = dalloc(&h->rowptr, h->n + 1)) || (rc = dalloc(&h->colind, h->nnz)) || (rc = dalloc(&h->vals, h->nnz)) ||
+      (rc = dalloc(&h->vals32, h->nnz)) || (rc = dalloc(&h->R, nk)) || (rc = dalloc(&h->P, nk)) ||
+      (rc = dalloc(&h->Q, nk)) || (rc = dalloc(&h->partA, partsz)) || (rc = dalloc(&h->partR, partsz)) ||
+      (rc = dalloc(&h->partN, partsz)) || (rc = dalloc(&h->alpha, pl.W)) || (rc = dalloc(&h->rho, pl.W)) ||
+      (rc = dalloc(&h->rnew, pl.W)) || (rc = dalloc(&h->lam, pl.E)) || (rc = dalloc(&h->beta, pl.E)) ||
+      (rc = dalloc(&h->lam32, pl.E)) || (rc = dalloc(&h->beta32, pl.E)) || (rc = dalloc(&h->ws, wssz)) ||
+      (rc = dalloc(&h->r0, k)) || (rc = dalloc(&h->ratios, k)) || (rc = dalloc(&h->scale, 1)) ||
+      (rc = dalloc(&h->st, 1))) {
+    free_all(h);
+    delete h;
+    return rc;
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&h->st_host), 2 * sizeof(DevState), hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming) != hipSuccess) {
+    free_all(h);
+    delete h;
+    return fail(BCG_EHIP, "pinned state or event allocation failed");
+  }
+  hipError_t e = hipMemcpy(h->rowptr, A->rowptr, sizeof(int32_t) * (h->n + 1), hipMemcpyDeviceToDevice);
+  if (e == hipSuccess) e = hipMemcpy(h->colind, A->colind, sizeof(int32_t) * h->nnz, hipMemcpyDeviceToDevice);
+  if (e == hipSuccess) e = hipMemcpy(h->vals, A->values, sizeof(double) * h->nnz, hipMemcpyDeviceToDevice);
+  if (e == hipSuccess) {
+    launch_cast_values(h->nnz, h->vals, h->vals32, nullptr);
+    e = hipDeviceSynchronize();
+  }
+  if (e != hipSuccess) {
+    free_all(h);
+    delete h;
+    return fail(BCG_EHIP, "copying the CSR matrix failed: %s", hipGetErrorString(e));
+  }
+  *out = h;
+  return BCG_OK;
+}
+
+void bcg_destroy(bcg_handle* h) {
+  if (!h) return;
+  DeviceGuard g(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  free_all(h);
+  delete h;
+}
+
+int bcg_set_stream(bcg_handle* h, void* hip_stream) {
+  if (!h) return fail(BCG_EINVAL, "handle is NULL");
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  return BCG_OK;
+}
+
+int bcg_set_precision(bcg_handle* h, int mode, double inner_tol, int inner_maxit, int max_outer) {
+  if (!h) return fail(BCG_EINVAL, "handle is NULL");
+  if (mode != BCG_FP64 && mode != BCG_FP32_REFINE) return fail(BCG_EINVAL, "unknown precision mode %d", mode);
+  if (!(inner_tol > 0.0 && inner_tol < 1.0)) return fail(BCG_EINVAL, "inner_tol must be in (0, 1)");
+  if (inner_maxit < 1 || max_outer < 1) return fail(BCG_EINVAL, "inner_maxit and max_outer must be >= 1");
+  h->precision = mode;
+  h->inner_tol = inner_tol;
+  h->inner_maxit = inner_maxit;
+  h->max_outer = max_outer;
+  return BCG_OK;
+}
+
+int bcg_solve(bcg_handle* h, const double* B, double* X, double tol, int maxit) {
+  g_error.clear();
+  if (!h) return fail(BCG_EINVAL, "handle is NULL");
+  if (!B || !X || static_cast<const void*>(B) == static_cast<const void*>(X))
+    return fail(BCG_EINVAL, "B and X must be distinct non-NULL device arrays");
+  if (!(tol >= 0.0) || !std::isfinite(tol) || maxit < 0) return fail(BCG_EINVAL, "tol must be finite >= 0, maxit >= 0");
+  DeviceGuard g(h->device);
+  const auto t0 = std::chrono::steady_clock::now();
+  h->info = bcg_info{};
+  h->info.k = h->k;
+  h->ref_r0.clear();
+  h->host_ratios.assign(h->k, 1.0);
+  int its = 0;
+  int rc = h->precision == BCG_FP32_REFINE ? solve_refine(h, B, X, tol, maxit) : solve_fp64(h, B, X, tol, maxit, nullptr, &its);
+  if (h->precision != BCG_FP32_REFINE) h->info.iterations = its;
+  const hipError_t se = hipStreamSynchronize(h->stream);
+  if (se != hipSuccess && rc >= 0) rc = fail(BCG_EHIP, "solve failed: %s", hipGetErrorString(se));
+  if (h->prof_on) prof_collect(h, 0);  // set-up launches still pending
+  // true residual of the returned X relative to ||R0_j||
+  if (rc != BCG_EINVAL && rc != BCG_EHIP && rc != BCG_ENOMEM && (int)h->ref_r0.size() == h->k) {
+    launch_residual(h->pl, h->rowptr, h->colind, h->vals, B, X, h->Q, nullptr, h->partN, 0, h->stream);
+    launch_reduce(h->pl, h->partN, h->rnew, h->pl.W, nullptr, h->stream);
+    std::vector<double> n2;
+    if (fetch_norms(h, h->rnew, n2) == BCG_OK) h->info.true_rel_res = max_ratio(n2, h->ref_r0);
+  }
+  double m = 0.0;
+  for (double v : h->host_ratios) m = std::max(m, v);
+  h->info.max_rel_res = m;
+  if (h->precision == BCG_FP32_REFINE) h->info.max_rel_res = h->info.true_rel_res;
+  h->info.status = rc;
+  h->info.converged = rc == BCG_OK;
+  h->info.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return rc;
+}
+
+int bcg_update_values(bcg_handle* h, const double* values) {
+  if (!h || !values) return fail(BCG_EINVAL, "handle and values must be non-NULL");
+  DeviceGuard g(h->device);
+  HIP_TRY(hipMemcpyAsync(h->vals, values, sizeof(double) * h->nnz, hipMemcpyDeviceToDevice, h->stream));
+  launch_cast_values(h->nnz, h->vals, h->vals32, h->stream);
+  HIP_TRY(hipGetLastError());
+  return BCG_OK;
+}
+
+int bcg_csr_outer(bcg_handle* h, const double* Y, const double* X, double alpha, double* out_vals) {
+  if (!h || !Y || !X || !out_vals) return fail(BCG_EINVAL, "NULL argument");
+  DeviceGuard g(h->device);
+  launch_sampled_outer(h->n, h->k, h->rowptr, h->colind, Y, X, alpha, out_vals, h->stream);
+  HIP_TRY(hipGetLastError());
+  return BCG_OK;
+}
+
+int bcg_set_profiling(bcg_handle* h, int enable) {
+  if (!h) return fail(BCG_EINVAL, "handle is NULL");
+  DeviceGuard g(h->device);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  prof_collect(h, -1);  // drop anything pending
+  if (enable)
+    for (auto& t : h->prof) t = bcg_kernel_time{0, 0.0};
+  h->prof_on = enable != 0;
+  h->prof_mask = static_cast<unsigned>(enable);
+  return BCG_OK;
+}
+
+int bcg_get_kernel_times(const bcg_handle* h, bcg_kernel_time* out, int count) {
+  if (!h || !out || count < 0) return fail(BCG_EINVAL, "NULL argument");
+  for (int i = 0; i < count && i < BCG_NUM_KERNEL_CLASSES; ++i) out[i] = h->prof[i];
+  return BCG_OK;
+}
+
+int bcg_get_info(const bcg_handle* h, bcg_info* info) {
+  if (!h || !info) return fail(BCG_EINVAL, "NULL argument");
+  *info = h->info;
+  return BCG_OK;
+}
+
+int bcg_get_column_ratios(const bcg_handle* h, double* ratios, int k) {
+  if (!h || !ratios || k != h->k) return fail(BCG_EINVAL, "ratios must hold exactly k values");
+  std::memcpy(ratios, h->host_ratios.data(), sizeof(double) * k);
+  return BCG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,217 @@
+"""GPU (HIP) path vs the FP64 oracle, element by element, through the C ABI.
+
+Tolerances (FP64): the two sides run the same recurrences with different
+summation orders, so they differ by rounding amplified along the iteration.
+Fixed-iteration iterates must agree to 1e-10 relative (Frobenius); converged
+solves (tol 1e-8) must stop at the same iteration (a tie at the stop boundary
+may shift it by one) and agree to 1e-8 relative, the accuracy the method
+itself delivers. Integer and CSR work is compared bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.bcg import solve as oracle_solve
+from oracle.grad import kappa_vjp as oracle_kappa_vjp, sampled_outer as oracle_sampled_outer
+from oracle.stencil import stencil_csr
+from tests.gpu_helpers import csr_to_dev, dev, host, log, rel
+from workload import WORKLOADS, cell_coefficients, rhs, rhs_for
+
+pytestmark = pytest.mark.gpu
+
+FIXED_TOL = 1e-10
+CONVERGED_TOL = 1e-8
+
+
+def _lib():
+    import paper_1912_11930_amd as P
+    return P
+
+
+def _solver(A, k, variant, p):
+    P = _lib()
+    return P.BCG(*csr_to_dev(A), k=k, subalgebra=variant, p=p)
+
+
+# ----------------------------------------------------------------- CSR (a0)
+@pytest.mark.parametrize("dim,N,sigma", [
+    (2, 1, 0.0), (2, 2, 1.0), (2, 3, 0.5), (3, 1, 0.0), (3, 2, 1.0), (3, 5, 1.0),
+    (2, 32, 0.0), (2, 512, 0.5), (3, 128, 0.0), (3, 192, 1.0),
+])
+def test_stencil_bitexact(dim, N, sigma):
+    log(f"stencil dim={dim} N={N} sigma={sigma}")
+    P = _lib()
+    kappa = None if sigma == 0 else cell_coefficients(dim, N, sigma)
+    A = stencil_csr(dim, N, kappa)
+    rp, ci, va = P.stencil(dim, N, None if kappa is None else dev(kappa))
+    assert np.array_equal(host(rp), A.indptr)
+    assert np.array_equal(host(ci), A.indices)
+    assert np.array_equal(host(va).view(np.uint64), A.data.view(np.uint64))
+
+
+# ------------------------------------------------ fixed-iteration iterates
+CASES_SMALL = [("block", 0), ("global", 1), ("global", 2), ("parallel", 1), ("hybrid", 2), ("hybrid", 4)]
+
+
+@pytest.mark.parametrize("variant,p", CASES_SMALL)
+@pytest.mark.parametrize("m", [1, 10, 50])
+def test_fixed_iterations_poisson2d_32(variant, p, m):
+    w = WORKLOADS["poisson2d_32_k8"]
+    log(f"fixed {variant} p={p} m={m}")
+    A = stencil_csr(w.dim, w.N)
+    B = rhs_for(w)
+    Xo, io = oracle_solve(A, B, variant, p, tol=0.0, maxit=m)
+    s = _solver(A, w.k, variant, p)
+    Xg, ig = s.solve(dev(B), tol=0.0, maxit=m)
+    assert ig["iterations"] == io["iterations"] == m
+    assert ig["status"] == io["status"] == oracle.NOT_CONVERGED
+    assert rel(host(Xg), Xo) <= FIXED_TOL
+    np.testing.assert_allclose(ig["ratios"], io["ratios"], rtol=1e-8, atol=0)
+
+
+# ragged tails and tile geometry: n not a multiple of the rows per tile, odd p
+# (no register blocking), products too large for the fused path
+KP_CASES = [
+    (1, "block", 0), (3, "hybrid", 3), (5, "parallel", 1), (6, "global", 3), (12, "hybrid", 3),
+    (12, "global", 4), (24, "hybrid", 8), (32, "block", 0), (40, "hybrid", 5), (64, "hybrid", 8),
+    (64, "global", 16), (96, "hybrid", 48), (128, "block", 0), (128, "hybrid", 16), (128, "global", 1),
+    (256, "hybrid", 16),
+]
+
+
+@pytest.mark.parametrize("k,variant,p", KP_CASES)
+def test_fixed_iterations_k_p_grid(k, variant, p):
+    log(f"k={k} {variant} p={p}")
+    N = 37 if k <= 64 else 23
+    A = stencil_csr(2, N, cell_coefficients(2, N, 0.7))
+    B = rhs(A.shape[0], k, "normal", seed=k)
+    m = 6
+    Xo, io = oracle_solve(A, B, variant, p, tol=0.0, maxit=m)
+    s = _solver(A, k, variant, p)
+    Xg, ig = s.solve(dev(B), tol=0.0, maxit=m)
+    assert ig["iterations"] == io["iterations"]
+    assert ig["status"] == io["status"]
+    assert rel(host(Xg), Xo) <= FIXED_TOL
+
+
+# ---------------------------------------------------- converged solutions
+def _converged_case(A, B, variant, p, tol=1e-8, maxit=5000):
+    Xo, io = oracle_solve(A, B, variant, p, tol=tol, maxit=maxit)
+    s = _solver(A, B.shape[1], variant, p)
+    Xg, ig = s.solve(dev(B), tol=tol, maxit=maxit)
+    assert io["status"] == oracle.OK
+    assert ig["status"] == oracle.OK, ig
+    if ig["iterations"] != io["iterations"]:
+        # a tie at the stop boundary: both sides must agree at the oracle's count
+        assert abs(ig["iterations"] - io["iterations"]) == 1
+        assert min(max(ig["ratios"]), max(io["ratios"])) <= tol * (1 + 1e-6)
+        Xg2, _ = s.solve(dev(B), tol=0.0, maxit=io["iterations"])
+        Xg = Xg2
+    assert rel(host(Xg), Xo) <= CONVERGED_TOL
+    assert ig["true_rel_res"] <= 100 * tol
+    return ig, io
+
+
+@pytest.mark.parametrize("variant,p", [("block", 0), ("global", 1), ("parallel", 1), ("hybrid", 2), ("hybrid", 4)])
+def test_converged_poisson2d_32(variant, p):
+    w = WORKLOADS["poisson2d_32_k8"]
+    log(f"converged {variant} p={p}")
+    _converged_case(stencil_csr(w.dim, w.N), rhs_for(w), variant, p, tol=w.tol)
+
+
+@pytest.mark.parametrize("variant,p", [("block", 0), ("global", 4), ("parallel", 1), ("hybrid", 4)])
+def test_converged_diffusion_ragged(variant, p):
+    log(f"converged diffusion {variant} p={p}")
+    A = stencil_csr(3, 13, cell_coefficients(3, 13, 1.0))
+    B = rhs(A.shape[0], 16, "normal")
+    _converged_case(A, B, variant, p)
+
+
+# ----------------------------------------------------------- status codes
+def test_status_codes_match_oracle():
+    P = _lib()
+    A = stencil_csr(2, 12)
+    B = rhs(A.shape[0], 4, "uniform")
+    s = _solver(A, 4, "block", 0)
+    # NaN in B
+    Bn = B.copy(); Bn[5, 2] = np.nan
+    with pytest.raises(P.BCGError) as e:
+        s.solve(dev(Bn))
+    assert e.value.status == oracle.EINVAL
+    # zero column in a non-diagonal subalgebra
+    Bz = B.copy(); Bz[:, 1] = 0.0
+    with pytest.raises(P.BCGError):
+        s.solve(dev(Bz))
+    # ... but fine for parallel, the zero lane stays zero
+    sp_ = _solver(A, 4, "parallel", 1)
+    Xz, iz = sp_.solve(dev(Bz), tol=1e-10, maxit=500)
+    Xo, io = oracle_solve(A, Bz, "parallel", 1, tol=1e-10, maxit=500)
+    assert iz["status"] == io["status"] == oracle.OK
+    assert np.all(host(Xz)[:, 1] == 0.0)
+    assert rel(host(Xz), Xo) <= CONVERGED_TOL
+    # all-zero B: immediate success
+    X0, i0 = s.solve(dev(np.zeros_like(B)))
+    assert i0["status"] == oracle.OK and i0["iterations"] == 0
+    # not converged
+    _, inc = s.solve(dev(B), tol=1e-14, maxit=3)
+    assert inc["status"] == oracle.NOT_CONVERGED and inc["iterations"] == 3
+    # breakdown: negative definite operator, X stays at X0
+    An = A.copy(); An.setdiag(-A.diagonal())
+    sn = _solver(An, 4, "block", 0)
+    Xb, ib = sn.solve(dev(B))
+    _, ob = oracle_solve(An, B, "block", 0)
+    assert ib["status"] == ob["status"] == oracle.EBREAKDOWN
+    assert ib["iterations"] == ob["iterations"] == 0
+    assert np.all(host(Xb) == 0.0)
+    # breakdown: rank-deficient block [b, b]
+    Bd = np.stack([B[:, 0], B[:, 0]], axis=1)
+    sd = _solver(A, 2, "block", 0)
+    _, idd = sd.solve(dev(Bd))
+    assert idd["status"] == oracle.EBREAKDOWN == oracle_solve(A, Bd, "block", 0)[1]["status"]
+    # invalid arguments
+    with pytest.raises(P.BCGError):
+        _solver(A, 4, "hybrid", 3)
+    with pytest.raises(P.BCGError):
+        s.solve(dev(B), tol=-1.0)
+
+
+def test_repeated_solves_bitwise_identical():
+    A = stencil_csr(3, 17, cell_coefficients(3, 17, 1.0))
+    B = rhs(A.shape[0], 16, "normal")
+    s = _solver(A, 16, "hybrid", 4)
+    X1, i1 = s.solve(dev(B), tol=1e-8)
+    X2, i2 = s.solve(dev(B), tol=1e-8)
+    assert i1["iterations"] == i2["iterations"]
+    assert np.array_equal(host(X1).view(np.uint64), host(X2).view(np.uint64))
+
+
+def test_warm_start_and_x0():
+    A = stencil_csr(2, 20, cell_coefficients(2, 20, 0.5))
+    B = rhs(A.shape[0], 8, "uniform")
+    X0 = 0.3 * rhs(A.shape[0], 8, "normal", seed=9)
+    Xo, io = oracle_solve(A, B, "hybrid", 4, tol=0.0, maxit=7, X0=X0)
+    s = _solver(A, 8, "hybrid", 4)
+    Xg, ig = s.solve(dev(B), X=dev(X0), tol=0.0, maxit=7)
+    assert rel(host(Xg), Xo) <= FIXED_TOL
+
+
+# --------------------------------------------------- gradient kernels (a10)
+def test_sampled_outer_matches_oracle():
+    A = stencil_csr(3, 9, cell_coefficients(3, 9, 1.0))
+    k = 12
+    Y = rhs(A.shape[0], k, "normal", seed=4)
+    X = rhs(A.shape[0], k, "normal", seed=5)
+    s = _solver(A, k, "block", 0)
+    out = host(s.csr_outer(dev(Y), dev(X), -1.0))
+    np.testing.assert_allclose(out, oracle_sampled_outer(A, Y, X, -1.0), rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("dim,N", [(2, 9), (3, 6), (2, 512)])
+def test_kappa_vjp_matches_oracle(dim, N):
+    P = _lib()
+    kappa = cell_coefficients(dim, N, 0.5)
+    A = stencil_csr(dim, N, kappa)
+    dv = np.random.default_rng(1).standard_normal(A.nnz)
+    g = host(P.stencil_kappa_vjp(dim, N, dev(kappa), dev(dv)))
+    np.testing.assert_allclose(g, oracle_kappa_vjp(dim, N, kappa, A, dv), rtol=1e-12, atol=1e-12)
