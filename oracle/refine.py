@@ -87,9 +87,10 @@ def inner_solve32(A32, R32, variant, p, inner_tol, inner_maxit):
     return X, inner_maxit, NOT_CONVERGED
 
 
-def solve(A, B, variant="block", p=0, tol=1e-8, maxit=100, inner_tol=1e-4, inner_maxit=1000,
+def solve(A, B, variant="block", p=0, tol=1e-8, maxit=50, inner_tol=1e-4, inner_maxit=1000,
           X0=None):
-    """Mixed-precision solve; returns (X, info) with FP64 X."""
+    """Mixed-precision solve; returns (X, info) with FP64 X. ``maxit`` caps the
+    refinement steps."""
     B = np.asarray(B, dtype=np.float64)
     n, k = B.shape
     X = np.zeros_like(B) if X0 is None else np.array(X0, dtype=np.float64, copy=True)
@@ -112,24 +113,28 @@ def solve(A, B, variant="block", p=0, tol=1e-8, maxit=100, inner_tol=1e-4, inner
         return X, info
     safe = np.where(r0 == 0.0, 1.0, r0)
     prev = np.inf
-    for outer in range(1, maxit + 1):
+    outer = 0
+    while True:
         c = np.sqrt(np.einsum("ij,ij->j", R, R))
         ratio = float(np.max(np.where(r0 == 0.0, 0.0, c / safe)))
         if ratio <= tol:
             info["true_ratio"] = ratio
             return X, info
-        if ratio > 0.5 * prev:
-            X, sub = solve64(A, B, variant, p, tol, maxit=100000, X0=X, ref_norms=r0)
-            info["fp64_fallback"] = True
-            info["iterations"] += sub["iterations"]
-            info["status"] = sub["status"]
+        stagnated = ratio > 0.5 * prev
+        if not stagnated and outer >= maxit:
+            info["status"] = NOT_CONVERGED
             return X, info
-        prev = ratio
-        s = float(np.max(c))
-        D, its, st = inner_solve32(A32, (R / s).astype(np.float32), variant, p, inner_tol, inner_maxit)
-        info["iterations"] += its
-        info["outer_iterations"] = outer
-        if st < 0:
+        D = None
+        if not stagnated:
+            outer += 1
+            prev = ratio
+            s = float(np.max(c))
+            D, its, st = inner_solve32(A32, (R / s).astype(np.float32), variant, p, inner_tol, inner_maxit)
+            info["iterations"] += its
+            info["outer_iterations"] = outer
+            if st < 0:
+                D = None
+        if D is None:
             X, sub = solve64(A, B, variant, p, tol, maxit=100000, X0=X, ref_norms=r0)
             info["fp64_fallback"] = True
             info["iterations"] += sub["iterations"]
@@ -137,5 +142,3 @@ def solve(A, B, variant="block", p=0, tol=1e-8, maxit=100, inner_tol=1e-4, inner
             return X, info
         X = X + s * D.astype(np.float64)
         R = B - A @ X
-    info["status"] = NOT_CONVERGED
-    return X, info
