@@ -25,6 +25,7 @@ COMMON = [
 ]
 SOURCES = {
     "bcg_kernels.hip": [],
+    "bcg_fast.hip": [],
     "bcg_solver.hip": [],
     # bit-exact face coefficients: every operation rounded once
     "bcg_stencil.hip": ["-ffp-contract=off"],

@@ -1,0 +1,436 @@
+// Row kernels of the block CG iteration specialised on k (compile time) and a
+// block size p <= 16, for gfx950.
+//
+// Mapping: each row of the n x k block vectors is handled by G = k/2 lanes,
+// each lane owning two adjacent columns (one 16-byte load per operand in
+// FP64, 8 bytes in FP32), so a wave covers 64/G rows per step and waves
+// stride over the rows. The coefficient blocks (lambda, beta) of a lane's two
+// columns stay in registers for the whole kernel. Where a lane needs the other
+// columns of its group (p > 2) it reads them from a wave-private LDS slab of
+// the rows it just loaded, so the main loop has no workgroup barrier.
+//
+// Block products: lane (row i, columns b0, b0+1 of group g) accumulates
+// sum_i X[i, g*p + a] * Y[i, b] for a < p over all of its rows, in FP64.
+// After the row loop the partial sums are combined across the row slots of
+// the wave (butterfly over lane bits) and across the four waves (fixed order)
+// and written as one packed partial [qo][p][p] (+ column norms) per
+// workgroup, the same layout as the generic kernels.
+#include <cstdlib>
+#include <type_traits>
+
+#include "../../include/bcg.h"
+#include "bcg_internal.h"
+
+namespace bcg {
+
+namespace {
+
+template <typename T>
+struct V2;
+template <>
+struct V2<double> {
+  using type = double2;
+};
+template <>
+struct V2<float> {
+  using type = float2;
+};
+
+__device__ __forceinline__ bool fstopped(const DevState* st) {
+  return st != nullptr && *reinterpret_cast<const volatile int*>(&st->done) != 0;
+}
+
+// Orders this wave's LDS writes before its later LDS reads.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int K, int P>
+struct Geo {
+  static constexpr int V = 2;            // columns per lane
+  static constexpr int G = K / V;        // lanes per row
+  static constexpr int RW = 64 / G;      // rows per wave step
+  static constexpr int SLAB = RW * K;    // elements of one wave slab
+  static constexpr int NEED_LDS = P > V; // group spans several lanes
+  static_assert(K % V == 0 && G <= 64 && 64 % G == 0, "unsupported k");
+  static_assert(P <= K && K % P == 0, "p must divide k");
+};
+
+// Per-lane partial block product and column norms.
+template <int P>
+struct LaneAcc {
+  double a[2][P];
+  double nrm[2];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+#pragma unroll
+      for (int j = 0; j < P; ++j) a[v][j] = 0.0;
+      nrm[v] = 0.0;
+    }
+  }
+};
+
+// acc[v][a] += X[g*p + a] * y[v]; xs points at the group's values of this
+// row (LDS) when p > 2, otherwise the lane's own two values are the group.
+template <typename T, int P>
+__device__ __forceinline__ void acc_row(LaneAcc<P>& acc, const T* xs, const T (&xo)[2], const T (&y)[2]) {
+  if constexpr (P == 1) {
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc.a[v][0] = fma((double)xo[v], (double)y[v], acc.a[v][0]);
+  } else if constexpr (P == 2) {
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc.a[v][j] = fma((double)xo[j], (double)y[v], acc.a[v][j]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const double xv = (double)xs[j];
+#pragma unroll
+      for (int v = 0; v < 2; ++v) acc.a[v][j] = fma(xv, (double)y[v], acc.a[v][j]);
+    }
+  }
+}
+
+// out[v] = sum_a X[g*p + a] * C[a][b_v] with the lane's coefficient columns.
+template <typename T, int P>
+__device__ __forceinline__ void apply_row(T (&out)[2], const T* xs, const T (&xo)[2], const T (&c)[2][P]) {
+  if constexpr (P == 1) {
+#pragma unroll
+    for (int v = 0; v < 2; ++v) out[v] = xo[v] * c[v][0];
+  } else if constexpr (P == 2) {
+#pragma unroll
+    for (int v = 0; v < 2; ++v) out[v] = fma(xo[1], c[v][1], xo[0] * c[v][0]);
+  } else {
+    T s0 = T(0), s1 = T(0);
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const T xv = xs[j];
+      s0 = fma(xv, c[0][j], s0);
+      s1 = fma(xv, c[1][j], s1);
+    }
+    out[0] = s0;
+    out[1] = s1;
+  }
+}
+
+// Coefficient columns of this lane: c[v][a] = C_g[a][b_v] (global: C_0).
+template <typename T, int P>
+__device__ __forceinline__ void load_coeff(T (&c)[2][P], const T* C, int c0, int global) {
+#pragma unroll
+  for (int v = 0; v < 2; ++v) {
+    const int col = c0 + v;
+    const int g = col / P, b = col - g * P;
+    const T* base = C + (global ? 0 : g * P * P) + b;
+#pragma unroll
+    for (int a = 0; a < P; ++a) c[v][a] = base[a * P];
+  }
+}
+
+// Combines the lane partials of a workgroup and writes its packed partial row.
+// H must hold K*P + K doubles of LDS.
+template <int K, int P, bool NORMS>
+__device__ void finish_partial(LaneAcc<P>& acc, double* H, double* prow, const Plan& pl) {
+  using Gm = Geo<K, P>;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // butterfly over the row slots of the wave (lane bits >= log2(G))
+#pragma unroll
+  for (int off = Gm::G; off < 64; off <<= 1) {
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+#pragma unroll
+      for (int j = 0; j < P; ++j) acc.a[v][j] += __shfl_xor(acc.a[v][j], off);
+      if (NORMS) acc.nrm[v] += __shfl_xor(acc.nrm[v], off);
+    }
+  }
+  const int c0 = 2 * lane;  // valid for lane < G
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w && lane < Gm::G) {
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int col = c0 + v, g = col / P, b = col - g * P;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          const int idx = g * P * P + j * P + b;
+          H[idx] = (w == 0 ? 0.0 : H[idx]) + acc.a[v][j];
+        }
+        if (NORMS) H[K * P + col] = (w == 0 ? 0.0 : H[K * P + col]) + acc.nrm[v];
+      }
+    }
+    __syncthreads();
+  }
+  const int E = pl.E;
+  constexpr int PP = P * P, Q = K / P;
+  for (int e = tid; e < E; e += kBlock) {
+    double s;
+    if (pl.global) {
+      s = H[e];
+      for (int g = 1; g < Q; ++g) s += H[g * PP + e];
+    } else {
+      s = H[e];
+    }
+    prow[e] = s;
+  }
+  if (NORMS)
+    for (int j = tid; j < K; j += kBlock) prow[E + j] = H[K * P + j];
+}
+
+// ---------------------------------------------------------------- SpMM
+template <typename T, int K, int P>
+__global__ __launch_bounds__(kBlock) void k_spmm_fast(Plan pl, const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ colind, const T* __restrict__ vals,
+                                                      const T* __restrict__ Pm, T* __restrict__ Q,
+                                                      double* __restrict__ part, const DevState* st) {
+  if (fstopped(st)) return;
+  using Gm = Geo<K, P>;
+  using T2 = typename V2<T>::type;
+  __shared__ T slab[4][Gm::NEED_LDS ? Gm::SLAB : 1];
+  __shared__ double H[K * P + K];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int rr = lane / Gm::G, cg = lane - rr * Gm::G, c0 = 2 * cg;
+  const int gcol = (c0 / P) * P;
+  LaneAcc<P> acc;
+  acc.zero();
+  const int64_t nsteps = (pl.n + Gm::RW - 1) / Gm::RW;
+  const int64_t tw = (int64_t)gridDim.x * 4;
+  for (int64_t s = (int64_t)blockIdx.x * 4 + wave; s < nsteps; s += tw) {
+    const int64_t i = s * Gm::RW + rr;
+    T q[2] = {T(0), T(0)}, po[2] = {T(0), T(0)};
+    if (i < pl.n) {
+      const int j0 = rowptr[i], j1 = rowptr[i + 1];
+      for (int jb = j0; jb < j1; jb += 8) {
+        int cols[8];
+        T vs[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const bool ok = jb + u < j1;
+          cols[u] = ok ? colind[jb + u] : 0;
+          vs[u] = ok ? vals[jb + u] : T(0);
+        }
+        T2 xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          xv[u] = (jb + u < j1) ? *reinterpret_cast<const T2*>(Pm + (int64_t)cols[u] * K + c0) : T2{T(0), T(0)};
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (jb + u < j1) {
+            q[0] = fma(vs[u], xv[u].x, q[0]);
+            q[1] = fma(vs[u], xv[u].y, q[1]);
+          }
+        }
+      }
+      *reinterpret_cast<T2*>(Q + i * K + c0) = T2{q[0], q[1]};
+      const T2 pv = *reinterpret_cast<const T2*>(Pm + i * K + c0);
+      po[0] = pv.x;
+      po[1] = pv.y;
+    }
+    const T* xs = nullptr;
+    if constexpr (Gm::NEED_LDS) {
+      T* sl = slab[wave];
+      *reinterpret_cast<T2*>(sl + rr * K + c0) = T2{po[0], po[1]};
+      wave_sync();
+      xs = sl + rr * K + gcol;
+    }
+    acc_row<T, P>(acc, xs, po, q);  // alpha = <<P, Q>>: a over P, b over Q
+    if constexpr (Gm::NEED_LDS) wave_sync();
+  }
+  finish_partial<K, P, false>(acc, H, part + (int64_t)blockIdx.x * pl.W, pl);
+}
+
+// ------------------------------------------------------ X, R update
+template <typename T, int K, int P>
+__global__ __launch_bounds__(kBlock) void k_update_xr_fast(Plan pl, T* __restrict__ X, T* __restrict__ R,
+                                                           const T* __restrict__ Pm, const T* __restrict__ Q,
+                                                           const T* __restrict__ lam, double* __restrict__ part,
+                                                           const DevState* st) {
+  if (fstopped(st)) return;
+  using Gm = Geo<K, P>;
+  using T2 = typename V2<T>::type;
+  __shared__ T slab[4][3][Gm::NEED_LDS ? Gm::SLAB : 1];
+  __shared__ double H[K * P + K];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int rr = lane / Gm::G, cg = lane - rr * Gm::G, c0 = 2 * cg;
+  const int gcol = (c0 / P) * P;
+  T cf[2][P];
+  load_coeff<T, P>(cf, lam, c0, pl.global);
+  LaneAcc<P> acc;
+  acc.zero();
+  const int64_t nsteps = (pl.n + Gm::RW - 1) / Gm::RW;
+  const int64_t tw = (int64_t)gridDim.x * 4;
+  for (int64_t s = (int64_t)blockIdx.x * 4 + wave; s < nsteps; s += tw) {
+    const int64_t i = s * Gm::RW + rr;
+    const bool ok = i < pl.n;
+    const int64_t off = i * K + c0;
+    T pv[2] = {T(0), T(0)}, qv[2] = {T(0), T(0)}, rv[2] = {T(0), T(0)}, xv[2] = {T(0), T(0)};
+    if (ok) {
+      const T2 a = *reinterpret_cast<const T2*>(Pm + off);
+      const T2 b = *reinterpret_cast<const T2*>(Q + off);
+      const T2 c = *reinterpret_cast<const T2*>(R + off);
+      const T2 d = *reinterpret_cast<const T2*>(X + off);
+      pv[0] = a.x; pv[1] = a.y;
+      qv[0] = b.x; qv[1] = b.y;
+      rv[0] = c.x; rv[1] = c.y;
+      xv[0] = d.x; xv[1] = d.y;
+    }
+    const T *ps = nullptr, *qs = nullptr, *rs = nullptr;
+    if constexpr (Gm::NEED_LDS) {
+      T* sp = slab[wave][0];
+      T* sq = slab[wave][1];
+      *reinterpret_cast<T2*>(sp + rr * K + c0) = T2{pv[0], pv[1]};
+      *reinterpret_cast<T2*>(sq + rr * K + c0) = T2{qv[0], qv[1]};
+      wave_sync();
+      ps = sp + rr * K + gcol;
+      qs = sq + rr * K + gcol;
+    }
+    T dx[2], dr[2];
+    apply_row<T, P>(dx, ps, pv, cf);
+    apply_row<T, P>(dr, qs, qv, cf);
+    T rn[2];
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      xv[v] = xv[v] + dx[v];   // X + P lambda
+      rn[v] = rv[v] - dr[v];   // R - Q lambda
+    }
+    if (ok) {
+      *reinterpret_cast<T2*>(X + off) = T2{xv[0], xv[1]};
+      *reinterpret_cast<T2*>(R + off) = T2{rn[0], rn[1]};
+    }
+    if constexpr (Gm::NEED_LDS) {
+      T* sr = slab[wave][2];
+      *reinterpret_cast<T2*>(sr + rr * K + c0) = T2{rn[0], rn[1]};
+      wave_sync();
+      rs = sr + rr * K + gcol;
+    }
+    acc_row<T, P>(acc, rs, rn, rn);  // <<R, R>>
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc.nrm[v] = fma((double)rn[v], (double)rn[v], acc.nrm[v]);
+    if constexpr (Gm::NEED_LDS) wave_sync();
+  }
+  finish_partial<K, P, true>(acc, H, part + (int64_t)blockIdx.x * pl.W, pl);
+}
+
+// ------------------------------------------------------------ P update
+template <typename T, int K, int P>
+__global__ __launch_bounds__(kBlock) void k_update_p_fast(Plan pl, T* __restrict__ Pm, const T* __restrict__ R,
+                                                          const T* __restrict__ beta, double* __restrict__ part,
+                                                          const DevState* st) {
+  if (fstopped(st)) return;
+  using Gm = Geo<K, P>;
+  using T2 = typename V2<T>::type;
+  __shared__ T slab[4][2][Gm::NEED_LDS ? Gm::SLAB : 1];
+  __shared__ double H[K * P + K];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int rr = lane / Gm::G, cg = lane - rr * Gm::G, c0 = 2 * cg;
+  const int gcol = (c0 / P) * P;
+  T cf[2][P];
+  load_coeff<T, P>(cf, beta, c0, pl.global);
+  LaneAcc<P> acc;
+  acc.zero();
+  const int64_t nsteps = (pl.n + Gm::RW - 1) / Gm::RW;
+  const int64_t tw = (int64_t)gridDim.x * 4;
+  for (int64_t s = (int64_t)blockIdx.x * 4 + wave; s < nsteps; s += tw) {
+    const int64_t i = s * Gm::RW + rr;
+    const bool ok = i < pl.n;
+    const int64_t off = i * K + c0;
+    T pv[2] = {T(0), T(0)}, rv[2] = {T(0), T(0)};
+    if (ok) {
+      const T2 a = *reinterpret_cast<const T2*>(Pm + off);
+      const T2 c = *reinterpret_cast<const T2*>(R + off);
+      pv[0] = a.x; pv[1] = a.y;
+      rv[0] = c.x; rv[1] = c.y;
+    }
+    const T *ps = nullptr, *ns = nullptr;
+    if constexpr (Gm::NEED_LDS) {
+      T* sp = slab[wave][0];
+      *reinterpret_cast<T2*>(sp + rr * K + c0) = T2{pv[0], pv[1]};
+      wave_sync();
+      ps = sp + rr * K + gcol;
+    }
+    T dp[2];
+    apply_row<T, P>(dp, ps, pv, cf);
+    T pn[2];
+#pragma unroll
+    for (int v = 0; v < 2; ++v) pn[v] = rv[v] + dp[v];  // R + P beta
+    if (ok) *reinterpret_cast<T2*>(Pm + off) = T2{pn[0], pn[1]};
+    if constexpr (Gm::NEED_LDS) {
+      T* sn = slab[wave][1];
+      *reinterpret_cast<T2*>(sn + rr * K + c0) = T2{pn[0], pn[1]};
+      wave_sync();
+      ns = sn + rr * K + gcol;
+    }
+    acc_row<T, P>(acc, ns, pn, rv);  // rho = <<P_new, R>>: a over P_new, b over R
+    if constexpr (Gm::NEED_LDS) wave_sync();
+  }
+  finish_partial<K, P, false>(acc, H, part + (int64_t)blockIdx.x * pl.W, pl);
+}
+
+template <typename F>
+bool dispatch_fast(const Plan& pl, F&& f) {
+  auto withP = [&](auto Kc) -> bool {
+    constexpr int K = decltype(Kc)::value;
+    switch (pl.p) {
+      case 1: f(Kc, std::integral_constant<int, 1>()); return true;
+      case 2: f(Kc, std::integral_constant<int, 2>()); return true;
+      case 4: if constexpr (K >= 4) { f(Kc, std::integral_constant<int, 4>()); return true; } return false;
+      case 8: if constexpr (K >= 8) { f(Kc, std::integral_constant<int, 8>()); return true; } return false;
+      case 16: if constexpr (K >= 16) { f(Kc, std::integral_constant<int, 16>()); return true; } return false;
+      default: return false;
+    }
+  };
+  switch (pl.k) {
+    case 8: return withP(std::integral_constant<int, 8>());
+    case 16: return withP(std::integral_constant<int, 16>());
+    case 32: return withP(std::integral_constant<int, 32>());
+    case 64: return withP(std::integral_constant<int, 64>());
+    case 128: return withP(std::integral_constant<int, 128>());
+    default: return false;
+  }
+}
+
+}  // namespace
+
+bool fast_supported(const Plan& pl) {
+  if (std::getenv("BCG_GENERIC_ONLY")) return false;
+  return dispatch_fast(pl, [](auto, auto) {});
+}
+
+template <typename T>
+void launch_spmm_fast(const Plan& pl, const int32_t* rowptr, const int32_t* colind, const T* vals, const T* P,
+                      T* Q, double* part, const DevState* st, hipStream_t s) {
+  dispatch_fast(pl, [&](auto Kc, auto Pc) {
+    hipLaunchKernelGGL((k_spmm_fast<T, decltype(Kc)::value, decltype(Pc)::value>), dim3(pl.nwg), dim3(kBlock), 0, s,
+                       pl, rowptr, colind, vals, P, Q, part, st);
+  });
+}
+
+template <typename T>
+void launch_update_xr_fast(const Plan& pl, T* X, T* R, const T* P, const T* Q, const T* lam, double* part,
+                           const DevState* st, hipStream_t s) {
+  dispatch_fast(pl, [&](auto Kc, auto Pc) {
+    hipLaunchKernelGGL((k_update_xr_fast<T, decltype(Kc)::value, decltype(Pc)::value>), dim3(pl.nwg), dim3(kBlock),
+                       0, s, pl, X, R, P, Q, lam, part, st);
+  });
+}
+
+template <typename T>
+void launch_update_p_fast(const Plan& pl, T* P, const T* R, const T* beta, double* part, const DevState* st,
+                          hipStream_t s) {
+  dispatch_fast(pl, [&](auto Kc, auto Pc) {
+    hipLaunchKernelGGL((k_update_p_fast<T, decltype(Kc)::value, decltype(Pc)::value>), dim3(pl.nwg), dim3(kBlock), 0,
+                       s, pl, P, R, beta, part, st);
+  });
+}
+
+#define BCG_FAST_INST(T)                                                                                           \
+  template void launch_spmm_fast<T>(const Plan&, const int32_t*, const int32_t*, const T*, const T*, T*, double*, \
+                                    const DevState*, hipStream_t);                                                 \
+  template void launch_update_xr_fast<T>(const Plan&, T*, T*, const T*, const T*, const T*, double*,              \
+                                         const DevState*, hipStream_t);                                            \
+  template void launch_update_p_fast<T>(const Plan&, T*, const T*, const T*, double*, const DevState*, hipStream_t);
+BCG_FAST_INST(double)
+BCG_FAST_INST(float)
+
+}  // namespace bcg

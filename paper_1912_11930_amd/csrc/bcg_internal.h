@@ -42,9 +42,11 @@ struct Plan {
   int TR;       // rows per LDS tile
   int64_t ntiles;
   int nwg;      // workgroups of the row kernels
+  int fast;     // 1: the k-specialised row kernels apply (k in {8..128}, p <= 16)
 };
 
 Plan make_plan(int64_t n, int k, int p, int global, int dec);
+bool fast_supported(const Plan& pl);
 
 // ---- launchers (all enqueue on `s`; none synchronises) ----
 // R = B - A X; norms partial; if with_p: P = R and <<R,R>> partial.
@@ -78,5 +80,15 @@ void launch_axpy_scaled(int64_t count, double* X, const float* D, const double* 
 void launch_sampled_outer(int64_t n, int k, const int32_t* rowptr, const int32_t* colind, const double* Y,
                           const double* X, double alpha, double* out, hipStream_t s);
 void launch_cast_values(int64_t nnz, const double* v, float* v32, hipStream_t s);
+// k-specialised row kernels (16-byte aligned block vectors; see fast_supported)
+template <typename T>
+void launch_spmm_fast(const Plan& pl, const int32_t* rowptr, const int32_t* colind, const T* vals, const T* P,
+                      T* Q, double* part, const DevState* st, hipStream_t s);
+template <typename T>
+void launch_update_xr_fast(const Plan& pl, T* X, T* R, const T* P, const T* Q, const T* lam, double* part,
+                           const DevState* st, hipStream_t s);
+template <typename T>
+void launch_update_p_fast(const Plan& pl, T* P, const T* R, const T* beta, double* part, const DevState* st,
+                          hipStream_t s);
 
 }  // namespace bcg

@@ -432,27 +432,44 @@ __global__ __launch_bounds__(kBlock) void k_product(Plan pl, const T* __restrict
 // Reductions and small solves
 // ------------------------------------------------------------------------
 
-// out[e] = sum over workgroups w (fixed order) of part[w][e], e < width.
-__global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ part, double* __restrict__ out,
-                                                   int width, int W, int nwg, const DevState* st) {
+// out[e] = sum over workgroups w of part[w][e], e < width, in a fixed order:
+// 16 row splits x 16 independent chains per entry, combined by fixed trees.
+constexpr int kRedThreads = 1024;
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict__ part, double* __restrict__ out,
+                                                        int width, int W, int nwg, const DevState* st) {
   if (stopped(st)) return;
-  __shared__ double sh[4][64];
-  const int tid = threadIdx.x, lane = tid & 63, s = tid >> 6;
+  __shared__ double sh[16][64];
+  const int tid = threadIdx.x, lane = tid & 63, s = tid >> 6;  // s: split 0..15
   const int e = blockIdx.x * 64 + lane;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  double c[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) c[u] = 0.0;
   if (e < width) {
-    int w = s;
-    for (; w + 12 < nwg; w += 16) {
-      a0 += part[(int64_t)w * W + e];
-      a1 += part[(int64_t)(w + 4) * W + e];
-      a2 += part[(int64_t)(w + 8) * W + e];
-      a3 += part[(int64_t)(w + 12) * W + e];
+    // rows w = s + 16*m, chain u = m % 16
+    int m = 0;
+    for (; s + 16 * (m + 15) < nwg; m += 16) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) c[u] += part[(int64_t)(s + 16 * (m + u)) * W + e];
     }
-    for (; w < nwg; w += 4) a0 += part[(int64_t)w * W + e];
+    for (int u = 0; s + 16 * (m + u) < nwg; ++u) c[u] += part[(int64_t)(s + 16 * (m + u)) * W + e];
   }
-  sh[s][lane] = (a0 + a1) + (a2 + a3);
+#pragma unroll
+  for (int w = 8; w > 0; w >>= 1)
+#pragma unroll
+    for (int u = 0; u < w; ++u) c[u] = c[u] + c[u + w];
+  sh[s][lane] = c[0];
   __syncthreads();
-  if (s == 0 && e < width) out[e] = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+  if (s == 0 && e < width) {
+    double t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) t[u] = sh[u][lane];
+#pragma unroll
+    for (int w = 8; w > 0; w >>= 1)
+#pragma unroll
+      for (int u = 0; u < w; ++u) t[u] = t[u] + t[u + w];
+    out[e] = t[0];
+  }
 }
 
 constexpr int kSmallLdsP = 48;  // p x p solves of up to this size run in LDS
@@ -693,6 +710,201 @@ __global__ __launch_bounds__(kBlock) void k_conv_beta(Plan pl, const double* __r
   }
 }
 
+// ---- one wave per p x p group (2 <= p <= 16): no workgroup barriers ----
+constexpr int kWaveP = 16;
+
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// lambda_g = sym(alpha_g)^{-1} rho_g by Cholesky (Algorithm 1 line 7).
+__global__ __launch_bounds__(kBlock) void k_solve_lambda_w(Plan pl, const double* __restrict__ alpha,
+                                                           const double* __restrict__ rho, double* __restrict__ lam,
+                                                           float* __restrict__ lam32, DevState* st) {
+  if (stopped(st)) return;
+  __shared__ double lds[4][2 * kWaveP * kWaveP];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, p = pl.p, pp = p * p;
+  const int g = blockIdx.x * 4 + wave;
+  if (g >= pl.qo) return;
+  double* M = lds[wave];
+  double* Y = M + pp;
+  const double* al = alpha + (int64_t)g * pp;
+  const double* rh = rho + (int64_t)g * pp;
+  bool bad = false;
+  for (int e = lane; e < pp; e += 64) {
+    const int i = e / p, j = e - i * p;
+    const double m = 0.5 * (al[i * p + j] + al[j * p + i]);
+    M[e] = m;
+    Y[e] = rh[e];
+    bad |= !isfinite(m) || !isfinite(rh[e]);
+  }
+  bad = __any(bad);
+  wsync();
+  for (int j = 0; j < p && !bad; ++j) {
+    const double ajj = M[j * p + j];
+    double sacc = 0.0;
+    for (int m = 0; m < j; ++m) sacc = fma(M[j * p + m], M[j * p + m], sacc);
+    const double d = ajj - sacc;
+    if (!isfinite(d) || !(d > p * DBL_EPSILON * ajj) || !(ajj > 0.0)) {
+      bad = true;
+      break;
+    }
+    const double ljj = sqrt(d);
+    wsync();
+    if (lane == j) M[j * p + j] = ljj;
+    if (lane > j && lane < p) {
+      double t = 0.0;
+      for (int m = 0; m < j; ++m) t = fma(M[lane * p + m], M[j * p + m], t);
+      M[lane * p + j] = (M[lane * p + j] - t) / ljj;
+    }
+    wsync();
+  }
+  if (bad) {
+    if (lane == 0) set_status(st, BCG_EBREAKDOWN);
+    return;
+  }
+  if (lane < p) {
+    const int c = lane;
+    for (int i = 0; i < p; ++i) {
+      double t = Y[i * p + c];
+      for (int m = 0; m < i; ++m) t -= M[i * p + m] * Y[m * p + c];
+      Y[i * p + c] = t / M[i * p + i];
+    }
+    for (int i = p - 1; i >= 0; --i) {
+      double t = Y[i * p + c];
+      for (int m = i + 1; m < p; ++m) t -= M[m * p + i] * Y[m * p + c];
+      Y[i * p + c] = t / M[i * p + i];
+    }
+  }
+  wsync();
+  double* lo = lam + (int64_t)g * pp;
+  float* lo32 = lam32 + (int64_t)g * pp;
+  for (int e = lane; e < pp; e += 64) {
+    lo[e] = Y[e];
+    lo32[e] = static_cast<float>(Y[e]);
+  }
+}
+
+// Stop rule, then beta_g = rho_g^{-1} rho_new_g by LU with partial pivoting
+// (first largest magnitude on ties), one wave per group.
+__global__ __launch_bounds__(kBlock) void k_conv_beta_w(Plan pl, const double* __restrict__ red_new,
+                                                        const double* __restrict__ r0,
+                                                        const double* __restrict__ rho_old, double* __restrict__ beta,
+                                                        float* __restrict__ beta32, double* __restrict__ ratios,
+                                                        DevState* st, double tol, int it, int maxit) {
+  if (stopped(st)) return;
+  const int tid = threadIdx.x, k = pl.k, p = pl.p, pp = p * p;
+  __shared__ double smax[kBlock];
+  __shared__ int sbad[kBlock];
+  __shared__ double lds[4][2 * kWaveP * kWaveP];
+  double mx = 0.0;
+  int bad = 0;
+  for (int j = tid; j < k; j += kBlock) {
+    const double c = red_new[pl.E + j];
+    const double rr = r0[j];
+    const double ratio = (rr == 0.0) ? 0.0 : sqrt(c) / rr;
+    if (!isfinite(ratio))
+      bad = 1;
+    else
+      mx = fmax(mx, ratio);
+    if (blockIdx.x == 0) ratios[j] = ratio;
+  }
+  smax[tid] = mx;
+  sbad[tid] = bad;
+  __syncthreads();
+  for (int s2 = kBlock / 2; s2 > 0; s2 >>= 1) {
+    if (tid < s2) {
+      smax[tid] = fmax(smax[tid], smax[tid + s2]);
+      sbad[tid] |= sbad[tid + s2];
+    }
+    __syncthreads();
+  }
+  const bool lead = blockIdx.x == 0 && tid == 0;
+  if (lead) {
+    st->iter = it;
+    st->max_ratio = sbad[0] ? NAN : smax[0];
+  }
+  if (sbad[0]) {
+    if (lead) set_status(st, BCG_EBREAKDOWN);
+    return;
+  }
+  if (smax[0] <= tol) {
+    if (lead) set_status(st, BCG_OK);
+    return;
+  }
+  if (it >= maxit) {
+    if (lead) set_status(st, BCG_NOT_CONVERGED);
+    return;
+  }
+  const int wave = tid >> 6, lane = tid & 63;
+  const int g = blockIdx.x * 4 + wave;
+  if (g >= pl.qo) return;
+  double* M = lds[wave];
+  double* Y = M + pp;
+  bool fail = false;
+  for (int e = lane; e < pp; e += 64) {
+    M[e] = rho_old[(int64_t)g * pp + e];
+    Y[e] = red_new[(int64_t)g * pp + e];
+    fail |= !isfinite(M[e]);
+  }
+  fail = __any(fail);
+  wsync();
+  for (int j = 0; j < p && !fail; ++j) {
+    // pivot: largest |M[i][j]|, i >= j, smallest i on ties
+    double v = (lane >= j && lane < p) ? fabs(M[lane * p + j]) : -1.0;
+    int idx = lane;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(v, off);
+      const int oi = __shfl_xor(idx, off);
+      if (ov > v || (ov == v && oi < idx)) {
+        v = ov;
+        idx = oi;
+      }
+    }
+    if (v == 0.0) {
+      fail = true;
+      break;
+    }
+    const int pr = idx;
+    if (pr != j) {
+      if (lane < p) {
+        double t = M[j * p + lane];
+        M[j * p + lane] = M[pr * p + lane];
+        M[pr * p + lane] = t;
+        t = Y[j * p + lane];
+        Y[j * p + lane] = Y[pr * p + lane];
+        Y[pr * p + lane] = t;
+      }
+      wsync();
+    }
+    if (lane > j && lane < p) {
+      const double l = M[lane * p + j] / M[j * p + j];
+      for (int c = j + 1; c < p; ++c) M[lane * p + c] -= l * M[j * p + c];
+      for (int c = 0; c < p; ++c) Y[lane * p + c] -= l * Y[j * p + c];
+    }
+    wsync();
+  }
+  if (fail) {
+    if (lane == 0) set_status(st, BCG_EBREAKDOWN);
+    return;
+  }
+  if (lane < p) {
+    const int c = lane;
+    for (int i = p - 1; i >= 0; --i) {
+      double t = Y[i * p + c];
+      for (int m2 = i + 1; m2 < p; ++m2) t -= M[i * p + m2] * Y[m2 * p + c];
+      Y[i * p + c] = t / M[i * p + i];
+    }
+  }
+  wsync();
+  for (int e = lane; e < pp; e += 64) {
+    beta[(int64_t)g * pp + e] = Y[e];
+    beta32[(int64_t)g * pp + e] = static_cast<float>(Y[e]);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_axpy_scaled(int64_t count, double* __restrict__ X,
                                                         const float* __restrict__ D, const double* __restrict__ scale) {
   const double s = *scale;
@@ -770,8 +982,13 @@ Plan make_plan(int64_t n, int k, int p, int global, int dec) {
   pl.fused = pl.nab <= kNabMax;
   pl.TR = kTileElems / k > 0 ? kTileElems / k : 1;
   pl.ntiles = (n + pl.TR - 1) / pl.TR;
-  pl.nwg = static_cast<int>(pl.ntiles < kMaxWG ? pl.ntiles : kMaxWG);
-  if (pl.nwg < 1) pl.nwg = 1;
+  // rows per wave step of the fast kernels (k/2 lanes per row), 4 waves per group
+  const int64_t rw = k >= 2 && k <= 128 ? 128 / k : 1;
+  const int64_t fwg = ((n + rw - 1) / rw + 3) / 4;
+  int64_t nwg = pl.ntiles < fwg ? pl.ntiles : fwg;
+  if (nwg > kMaxWG) nwg = kMaxWG;
+  pl.nwg = static_cast<int>(nwg < 1 ? 1 : nwg);
+  pl.fast = fast_supported(pl);
   return pl;
 }
 
@@ -830,11 +1047,15 @@ void launch_product(const Plan& pl, const T* X, const T* Y, double* part, const 
 }
 
 void launch_reduce(const Plan& pl, const double* part, double* out, int width, const DevState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3((width + 63) / 64), dim3(kBlock), 0, s, part, out, width, pl.W, pl.nwg, st);
+  hipLaunchKernelGGL(k_reduce, dim3((width + 63) / 64), dim3(kRedThreads), 0, s, part, out, width, pl.W, pl.nwg, st);
 }
 
 void launch_solve_lambda(const Plan& pl, const double* alpha, const double* rho, double* lam, float* lam32,
                          double* ws, DevState* st, hipStream_t s) {
+  if (pl.p >= 2 && pl.p <= kWaveP) {
+    hipLaunchKernelGGL(k_solve_lambda_w, dim3((pl.qo + 3) / 4), dim3(kBlock), 0, s, pl, alpha, rho, lam, lam32, st);
+    return;
+  }
   const int grid = pl.p == 1 ? 1 : pl.qo;
   hipLaunchKernelGGL(k_solve_lambda, dim3(grid), dim3(kBlock), 0, s, pl, alpha, rho, lam, lam32, ws, st);
 }
@@ -842,6 +1063,11 @@ void launch_solve_lambda(const Plan& pl, const double* alpha, const double* rho,
 void launch_conv_beta(const Plan& pl, const double* red_new, const double* r0, const double* rho_old, double* beta,
                       float* beta32, double* ws, double* ratios, DevState* st, double tol, int it, int maxit,
                       hipStream_t s) {
+  if (pl.p >= 2 && pl.p <= kWaveP) {
+    hipLaunchKernelGGL(k_conv_beta_w, dim3((pl.qo + 3) / 4), dim3(kBlock), 0, s, pl, red_new, r0, rho_old, beta,
+                       beta32, ratios, st, tol, it, maxit);
+    return;
+  }
   const int grid = pl.p == 1 ? 1 : pl.qo;
   hipLaunchKernelGGL(k_conv_beta, dim3(grid), dim3(kBlock), 0, s, pl, red_new, r0, rho_old, beta, beta32, ws, ratios,
                      st, tol, it, maxit);

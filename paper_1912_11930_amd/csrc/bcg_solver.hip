@@ -101,6 +101,7 @@ struct bcg_handle {
   int inner_maxit = 1000, max_outer = 50;
   float *R32 = nullptr, *P32 = nullptr, *Q32 = nullptr, *D32 = nullptr;
   int chunk = 32;       // upper bound on iterations enqueued per poll
+  bool fast_now = false;  // k-specialised row kernels for the current solve
   // per-kernel-class event timing
   struct ProfRec {
     int cls, it;
@@ -214,26 +215,39 @@ template <typename T>
 void enqueue_iteration(bcg_handle* h, const IterBuffers<T>& b, double tol, int it, int maxit) {
   const Plan& pl = h->pl;
   hipStream_t s = h->stream;
+  const bool fast = h->fast_now;
   timed(h, BCG_K_SPMM, it, [&] {  // lines 4-5
-    launch_spmm_product<T>(pl, h->rowptr, h->colind, b.vals, b.P, b.Q, h->partA, h->st, s);
+    if (fast)
+      launch_spmm_fast<T>(pl, h->rowptr, h->colind, b.vals, b.P, b.Q, h->partA, h->st, s);
+    else
+      launch_spmm_product<T>(pl, h->rowptr, h->colind, b.vals, b.P, b.Q, h->partA, h->st, s);
   });
-  if (!pl.fused) timed(h, BCG_K_PRODUCT, it, [&] { launch_product<T>(pl, b.P, b.Q, h->partA, h->st, s); });
+  if (!fast && !pl.fused) timed(h, BCG_K_PRODUCT, it, [&] { launch_product<T>(pl, b.P, b.Q, h->partA, h->st, s); });
   timed(h, BCG_K_REDUCE, it, [&] { launch_reduce(pl, h->partA, h->alpha, pl.E, h->st, s); });
   timed(h, BCG_K_SMALL, it, [&] {  // line 7
     launch_solve_lambda(pl, h->alpha, h->rho, h->lam, h->lam32, h->ws, h->st, s);
   });
   timed(h, BCG_K_UPDATE_XR, it, [&] {  // lines 8-9 and the product of line 11
-    launch_update_xr<T>(pl, b.X, b.R, b.P, b.Q, b.lam, h->partN, h->st, s);
+    if (fast)
+      launch_update_xr_fast<T>(pl, b.X, b.R, b.P, b.Q, b.lam, h->partN, h->st, s);
+    else
+      launch_update_xr<T>(pl, b.X, b.R, b.P, b.Q, b.lam, h->partN, h->st, s);
   });
-  if (!pl.fused) timed(h, BCG_K_PRODUCT, it, [&] { launch_product<T>(pl, b.R, b.R, h->partN, h->st, s); });
+  if (!fast && !pl.fused) timed(h, BCG_K_PRODUCT, it, [&] { launch_product<T>(pl, b.R, b.R, h->partN, h->st, s); });
   timed(h, BCG_K_REDUCE, it, [&] { launch_reduce(pl, h->partN, h->rnew, pl.W, h->st, s); });
   timed(h, BCG_K_SMALL, it, [&] {  // stop rule, line 12
     launch_conv_beta(pl, h->rnew, h->r0, h->rho, h->beta, h->beta32, h->ws, h->ratios, h->st, tol, it, maxit, s);
   });
   // line 13 and the recomputed rho of line 6 for the next iteration; after
   // the last iteration these launches return at entry
-  timed(h, BCG_K_UPDATE_P, it + 1, [&] { launch_update_p<T>(pl, b.P, b.R, b.beta, h->partR, h->st, s); });
-  if (!pl.fused) timed(h, BCG_K_PRODUCT, it + 1, [&] { launch_product<T>(pl, b.P, b.R, h->partR, h->st, s); });
+  timed(h, BCG_K_UPDATE_P, it + 1, [&] {
+    if (fast)
+      launch_update_p_fast<T>(pl, b.P, b.R, b.beta, h->partR, h->st, s);
+    else
+      launch_update_p<T>(pl, b.P, b.R, b.beta, h->partR, h->st, s);
+  });
+  if (!fast && !pl.fused)
+    timed(h, BCG_K_PRODUCT, it + 1, [&] { launch_product<T>(pl, b.P, b.R, h->partR, h->st, s); });
   timed(h, BCG_K_REDUCE, it + 1, [&] { launch_reduce(pl, h->partR, h->rho, pl.E, h->st, s); });
 }
 
@@ -364,6 +378,7 @@ int solve_fp64(bcg_handle* h, const double* B, double* X, double tol, int maxit,
   if (all_zero) return BCG_OK;
   if (maxit == 0) return BCG_NOT_CONVERGED;
   IterBuffers<double> b{h->vals, X, h->R, h->P, h->Q, h->lam, h->beta};
+  h->fast_now = h->pl.fast && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
   DevState fin{};
   if ((rc = run_iterations<double>(h, b, tol, maxit, &fin))) return rc;
   *iterations = fin.iter;
@@ -419,6 +434,7 @@ int solve_refine(bcg_handle* h, const double* B, double* X, double tol, int maxi
         return rc;
       } else {
         IterBuffers<float> b{h->vals32, h->D32, h->R32, h->P32, h->Q32, h->lam32, h->beta32};
+        h->fast_now = h->pl.fast;
         DevState fin{};
         if ((rc = run_iterations<float>(h, b, h->inner_tol, h->inner_maxit, &fin))) return rc;
         info.iterations += fin.iter;

@@ -215,3 +215,49 @@ def test_kappa_vjp_matches_oracle(dim, N):
     dv = np.random.default_rng(1).standard_normal(A.nnz)
     g = host(P.stencil_kappa_vjp(dim, N, dev(kappa), dev(dv)))
     np.testing.assert_allclose(g, oracle_kappa_vjp(dim, N, kappa, A, dv), rtol=1e-12, atol=1e-12)
+
+
+# --------------------------------------------- k-specialised row kernels
+FAST_CASES = [(k, v, p) for k in (8, 16, 32, 64, 128) for (v, p) in
+              [("parallel", 1), ("hybrid", 2), ("hybrid", 4), ("hybrid", 8), ("hybrid", 16), ("global", 4)]
+              if p <= k] + [(8, "block", 0), (16, "block", 0), (16, "global", 1), (128, "global", 8)]
+
+
+@pytest.mark.parametrize("k,variant,p", FAST_CASES)
+def test_fast_path_fixed_iterations(k, variant, p):
+    log(f"fast k={k} {variant} p={p}")
+    N = 41 if k <= 32 else 19                      # ragged: n not a multiple of the rows per step
+    A = stencil_csr(2, N, cell_coefficients(2, N, 0.8))
+    B = rhs(A.shape[0], k, "normal", seed=100 + k)
+    m = 8
+    Xo, io = oracle_solve(A, B, variant, p, tol=0.0, maxit=m)
+    s = _solver(A, k, variant, p)
+    Xg, ig = s.solve(dev(B), tol=0.0, maxit=m)
+    assert ig["iterations"] == io["iterations"] == m
+    assert rel(host(Xg), Xo) <= FIXED_TOL
+
+
+@pytest.mark.parametrize("k,variant,p", [(8, "block", 0), (16, "hybrid", 4), (64, "hybrid", 8), (128, "global", 1)])
+def test_generic_path_forced(monkeypatch, k, variant, p):
+    # the generic LDS-tiled kernels stay correct for shapes the fast path also covers
+    monkeypatch.setenv("BCG_GENERIC_ONLY", "1")
+    log(f"generic k={k} {variant} p={p}")
+    A = stencil_csr(2, 29, cell_coefficients(2, 29, 0.8))
+    B = rhs(A.shape[0], k, "normal", seed=7)
+    Xo, io = oracle_solve(A, B, variant, p, tol=0.0, maxit=8)
+    s = _solver(A, k, variant, p)
+    Xg, ig = s.solve(dev(B), tol=0.0, maxit=8)
+    assert rel(host(Xg), Xo) <= FIXED_TOL
+
+
+def test_misaligned_x_uses_generic_path():
+    # a solution view that is not 16-byte aligned is still solved correctly
+    A = stencil_csr(2, 17)
+    k = 8
+    B = rhs(A.shape[0], k, "uniform")
+    Xo, _ = oracle_solve(A, B, "hybrid", 4, tol=0.0, maxit=6)
+    buf = torch.zeros(A.shape[0] * k + 1, dtype=torch.float64, device="cuda")
+    Xv = buf[1:].view(A.shape[0], k)
+    s = _solver(A, k, "hybrid", 4)
+    s.solve(dev(B), X=Xv, tol=0.0, maxit=6)
+    assert rel(host(Xv), Xo) <= FIXED_TOL
