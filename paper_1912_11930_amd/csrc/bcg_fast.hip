@@ -58,6 +58,33 @@ struct Geo {
   static_assert(P <= K && K % P == 0, "p must divide k");
 };
 
+// Row steps of this wave. Workgroups are dispatched to the 8 XCDs round
+// robin (workgroup b on XCD b % 8), so with at least 8 workgroups XCD x is
+// given the contiguous eighth x of the row steps: the neighbour rows a
+// stencil row gathers are then mostly its own, and stay in its L2.
+struct StepRange {
+  int64_t first, end, stride;
+};
+
+__device__ __forceinline__ StepRange wave_steps(int64_t nsteps) {
+  const int nwg = gridDim.x, b = blockIdx.x, wave = threadIdx.x >> 6;
+  StepRange r;
+  if (nwg < 8) {
+    r.first = (int64_t)b * 4 + wave;
+    r.end = nsteps;
+    r.stride = (int64_t)nwg * 4;
+    return r;
+  }
+  const int x = b & 7, lb = b >> 3;
+  const int nx = (nwg - x + 7) >> 3;  // workgroups on XCD x
+  const int64_t per = (nsteps + 7) / 8;
+  const int64_t lo = min((int64_t)x * per, nsteps);
+  r.first = lo + (int64_t)lb * 4 + wave;
+  r.end = min(lo + per, nsteps);
+  r.stride = (int64_t)nx * 4;
+  return r;
+}
+
 // Per-lane partial block product and column norms.
 template <int P>
 struct LaneAcc {
@@ -179,6 +206,82 @@ __device__ void finish_partial(LaneAcc<P>& acc, double* H, double* prow, const P
 }
 
 // ---------------------------------------------------------------- SpMM
+// Indices of one row step: the CSR range and up to 8 (column, value) pairs of
+// each lane's row, clamped to the row so every load is in bounds.
+template <typename T>
+struct RowIdx {
+  int j0, j1;
+  int cols[8];
+  T vs[8];
+};
+
+template <typename T>
+__device__ __forceinline__ void load_idx(RowIdx<T>& r, const int32_t* __restrict__ colind,
+                                         const T* __restrict__ vals, int jb) {
+  // entries past the row end (or of an empty row) re-read a valid entry of
+  // the matrix; their products are masked out by the caller
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int jj = max(min(jb + u, r.j1 - 1), 0);
+    r.cols[u] = colind[jj];
+    r.vs[u] = vals[jj];
+  }
+}
+
+// Broadcast of lane `src` of each aligned group of G lanes (G <= 32) through
+// the LDS crossbar (ds_swizzle bit mode: lane = (lane & and) | or).
+template <int G, int SRC>
+__device__ __forceinline__ int bcast_i(int x) {
+  static_assert(G <= 32 && SRC < G, "group broadcast within 32 lanes");
+  constexpr int pattern = (SRC << 5) | (0x1F & ~(G - 1));
+  return __builtin_amdgcn_ds_swizzle(x, pattern);
+}
+
+template <int G, int SRC>
+__device__ __forceinline__ double bcast_v(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = bcast_i<G, SRC>(static_cast<int>(v & 0xffffffffLL));
+  const int hi = bcast_i<G, SRC>(static_cast<int>(v >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+template <int G, int SRC>
+__device__ __forceinline__ float bcast_v(float x) {
+  return __int_as_float(bcast_i<G, SRC>(__float_as_int(x)));
+}
+
+// Cooperative index chunk: lane cg of a row group (G lanes) loads entry
+// jb + cg (+ jb + cg + G for G < 8); entry u then comes from lane u % G.
+template <typename T, int G>
+struct CoopIdx {
+  static constexpr int PER = G >= 8 ? 1 : 8 / G;
+  int c[PER];
+  T v[PER];
+  __device__ __forceinline__ void load(const int32_t* __restrict__ colind, const T* __restrict__ vals, int jb,
+                                       int j1, int cg) {
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int jj = max(min(jb + cg + t * G, j1 - 1), 0);
+      c[t] = colind[jj];
+      v[t] = vals[jj];
+    }
+  }
+  template <int U = 0>
+  __device__ __forceinline__ void spread(RowIdx<T>& r) {
+    if constexpr (U < 8) {
+      r.cols[U] = bcast_i<G, U % G>(c[U / G]);
+      r.vs[U] = bcast_v<G, U % G>(v[U / G]);
+      spread<U + 1>(r);
+    }
+  }
+};
+
+// Q = A P with the partial alpha = <<P, Q>>. Software pipelined so that no
+// wait on a younger load also waits for the current gathers (the vector
+// memory counter retires loads in issue order): per step the wave issues the
+// gathers of step s, then the first index chunk of step s+1 (its CSR range
+// was loaded one step earlier), then the CSR range of step s+2, and only then
+// consumes the gathers.
 template <typename T, int K, int P>
 __global__ __launch_bounds__(kBlock) void k_spmm_fast(Plan pl, const int32_t* __restrict__ rowptr,
                                                       const int32_t* __restrict__ colind, const T* __restrict__ vals,
@@ -195,37 +298,92 @@ __global__ __launch_bounds__(kBlock) void k_spmm_fast(Plan pl, const int32_t* __
   LaneAcc<P> acc;
   acc.zero();
   const int64_t nsteps = (pl.n + Gm::RW - 1) / Gm::RW;
-  const int64_t tw = (int64_t)gridDim.x * 4;
-  for (int64_t s = (int64_t)blockIdx.x * 4 + wave; s < nsteps; s += tw) {
+  const StepRange sr = wave_steps(nsteps);
+  const int64_t tw = sr.stride;
+  const int64_t n = pl.n;
+  // rows past n (last step) use row n-1 for their loads and are discarded
+  auto row_of = [&](int64_t step) -> int64_t {
+    const int64_t i = step * Gm::RW + rr;
+    return i < n ? i : n - 1;
+  };
+  // all loads of the loop are unconditional (clamped rows and entries), so
+  // the compiler's load-counter waits are exact
+  const int64_t last = sr.end > sr.first ? sr.end - 1 : sr.first;
+  int64_t s = sr.first;
+  RowIdx<T> cur;
+  int nj0 = 0, nj1 = 0;  // CSR range of step s + tw
+  if (s < sr.end) {
+    const int64_t i = row_of(s);
+    cur.j0 = rowptr[i];
+    cur.j1 = rowptr[i + 1];
+    const int64_t i1 = row_of(min(s + tw, last));
+    nj0 = rowptr[i1];
+    nj1 = rowptr[i1 + 1];
+    if constexpr (Gm::G <= 32) {
+      CoopIdx<T, Gm::G> ci;
+      ci.load(colind, vals, cur.j0, cur.j1, cg);
+      ci.spread(cur);
+    } else {
+      load_idx(cur, colind, vals, cur.j0);
+    }
+  }
+  for (; s < sr.end; s += tw) {
     const int64_t i = s * Gm::RW + rr;
-    T q[2] = {T(0), T(0)}, po[2] = {T(0), T(0)};
-    if (i < pl.n) {
-      const int j0 = rowptr[i], j1 = rowptr[i + 1];
-      for (int jb = j0; jb < j1; jb += 8) {
-        int cols[8];
-        T vs[8];
+    const bool ok = i < n;
+    const int64_t ic = ok ? i : n - 1;
+    // 1. gathers of the current step and its own row of P
+    T2 xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xv[u] = *reinterpret_cast<const T2*>(Pm + (int64_t)cur.cols[u] * K + c0);
+    const T2 pv = *reinterpret_cast<const T2*>(Pm + ic * K + c0);
+    // 2. index chunk of the next step (CSR range already loaded)
+    RowIdx<T> nxt;
+    nxt.j0 = nj0;
+    nxt.j1 = nj1;
+    CoopIdx<T, (Gm::G <= 32 ? Gm::G : 32)> cnx;
+    if constexpr (Gm::G <= 32)
+      cnx.load(colind, vals, nj0, nj1, cg);
+    else
+      load_idx(nxt, colind, vals, nj0);
+    // 3. CSR range two steps ahead
+    const int64_t i2 = row_of(min(s + 2 * tw, last));
+    nj0 = rowptr[i2];
+    nj1 = rowptr[i2 + 1];
+    // 4. consume the gathers
+    T q[2] = {T(0), T(0)};
+    {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool in = cur.j0 + u < cur.j1;
+        const T a0 = fma(cur.vs[u], xv[u].x, q[0]);
+        const T a1 = fma(cur.vs[u], xv[u].y, q[1]);
+        q[0] = in ? a0 : q[0];
+        q[1] = in ? a1 : q[1];
+      }
+      // rows with more than 8 entries: remaining chunks without pipelining
+      for (int jb = cur.j0 + 8; jb < cur.j1; jb += 8) {
+        RowIdx<T> ex;
+        ex.j1 = cur.j1;
+        load_idx(ex, colind, vals, jb);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xv[u] = *reinterpret_cast<const T2*>(Pm + (int64_t)ex.cols[u] * K + c0);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          const bool ok = jb + u < j1;
-          cols[u] = ok ? colind[jb + u] : 0;
-          vs[u] = ok ? vals[jb + u] : T(0);
-        }
-        T2 xv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-          xv[u] = (jb + u < j1) ? *reinterpret_cast<const T2*>(Pm + (int64_t)cols[u] * K + c0) : T2{T(0), T(0)};
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          if (jb + u < j1) {
-            q[0] = fma(vs[u], xv[u].x, q[0]);
-            q[1] = fma(vs[u], xv[u].y, q[1]);
-          }
+          const bool in = jb + u < cur.j1;
+          const T a0 = fma(ex.vs[u], xv[u].x, q[0]);
+          const T a1 = fma(ex.vs[u], xv[u].y, q[1]);
+          q[0] = in ? a0 : q[0];
+          q[1] = in ? a1 : q[1];
         }
       }
+    }
+    T po[2] = {T(0), T(0)};
+    if (ok) {
       *reinterpret_cast<T2*>(Q + i * K + c0) = T2{q[0], q[1]};
-      const T2 pv = *reinterpret_cast<const T2*>(Pm + i * K + c0);
       po[0] = pv.x;
       po[1] = pv.y;
+    } else {
+      q[0] = q[1] = T(0);
     }
     const T* xs = nullptr;
     if constexpr (Gm::NEED_LDS) {
@@ -236,6 +394,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_fast(Plan pl, const int32_t* __
     }
     acc_row<T, P>(acc, xs, po, q);  // alpha = <<P, Q>>: a over P, b over Q
     if constexpr (Gm::NEED_LDS) wave_sync();
+    if constexpr (Gm::G <= 32) cnx.spread(nxt);
+    cur = nxt;
   }
   finish_partial<K, P, false>(acc, H, part + (int64_t)blockIdx.x * pl.W, pl);
 }
@@ -259,21 +419,39 @@ __global__ __launch_bounds__(kBlock) void k_update_xr_fast(Plan pl, T* __restric
   LaneAcc<P> acc;
   acc.zero();
   const int64_t nsteps = (pl.n + Gm::RW - 1) / Gm::RW;
-  const int64_t tw = (int64_t)gridDim.x * 4;
-  for (int64_t s = (int64_t)blockIdx.x * 4 + wave; s < nsteps; s += tw) {
+  const StepRange sr = wave_steps(nsteps);
+  const int64_t tw = sr.stride;
+  const int64_t n = pl.n;
+  int64_t s = sr.first;
+  // operands of the next row step are loaded before the current one is used
+  T2 na{}, nb{}, nc{}, nd{};
+  if (s < sr.end) {
     const int64_t i = s * Gm::RW + rr;
-    const bool ok = i < pl.n;
+    const int64_t off = (i < n ? i : n - 1) * K + c0;
+    na = *reinterpret_cast<const T2*>(Pm + off);
+    nb = *reinterpret_cast<const T2*>(Q + off);
+    nc = *reinterpret_cast<const T2*>(R + off);
+    nd = *reinterpret_cast<const T2*>(X + off);
+  }
+  for (; s < sr.end; s += tw) {
+    const int64_t i = s * Gm::RW + rr;
+    const bool ok = i < n;
     const int64_t off = i * K + c0;
     T pv[2] = {T(0), T(0)}, qv[2] = {T(0), T(0)}, rv[2] = {T(0), T(0)}, xv[2] = {T(0), T(0)};
     if (ok) {
-      const T2 a = *reinterpret_cast<const T2*>(Pm + off);
-      const T2 b = *reinterpret_cast<const T2*>(Q + off);
-      const T2 c = *reinterpret_cast<const T2*>(R + off);
-      const T2 d = *reinterpret_cast<const T2*>(X + off);
-      pv[0] = a.x; pv[1] = a.y;
-      qv[0] = b.x; qv[1] = b.y;
-      rv[0] = c.x; rv[1] = c.y;
-      xv[0] = d.x; xv[1] = d.y;
+      pv[0] = na.x; pv[1] = na.y;
+      qv[0] = nb.x; qv[1] = nb.y;
+      rv[0] = nc.x; rv[1] = nc.y;
+      xv[0] = nd.x; xv[1] = nd.y;
+    }
+    const int64_t sn = s + tw;
+    if (sn < sr.end) {
+      const int64_t in = sn * Gm::RW + rr;
+      const int64_t offn = (in < n ? in : n - 1) * K + c0;
+      na = *reinterpret_cast<const T2*>(Pm + offn);
+      nb = *reinterpret_cast<const T2*>(Q + offn);
+      nc = *reinterpret_cast<const T2*>(R + offn);
+      nd = *reinterpret_cast<const T2*>(X + offn);
     }
     const T *ps = nullptr, *qs = nullptr, *rs = nullptr;
     if constexpr (Gm::NEED_LDS) {
@@ -330,17 +508,32 @@ __global__ __launch_bounds__(kBlock) void k_update_p_fast(Plan pl, T* __restrict
   LaneAcc<P> acc;
   acc.zero();
   const int64_t nsteps = (pl.n + Gm::RW - 1) / Gm::RW;
-  const int64_t tw = (int64_t)gridDim.x * 4;
-  for (int64_t s = (int64_t)blockIdx.x * 4 + wave; s < nsteps; s += tw) {
+  const StepRange sr = wave_steps(nsteps);
+  const int64_t tw = sr.stride;
+  const int64_t n = pl.n;
+  int64_t s = sr.first;
+  T2 na{}, nc{};
+  if (s < sr.end) {
     const int64_t i = s * Gm::RW + rr;
-    const bool ok = i < pl.n;
+    const int64_t off = (i < n ? i : n - 1) * K + c0;
+    na = *reinterpret_cast<const T2*>(Pm + off);
+    nc = *reinterpret_cast<const T2*>(R + off);
+  }
+  for (; s < sr.end; s += tw) {
+    const int64_t i = s * Gm::RW + rr;
+    const bool ok = i < n;
     const int64_t off = i * K + c0;
     T pv[2] = {T(0), T(0)}, rv[2] = {T(0), T(0)};
     if (ok) {
-      const T2 a = *reinterpret_cast<const T2*>(Pm + off);
-      const T2 c = *reinterpret_cast<const T2*>(R + off);
-      pv[0] = a.x; pv[1] = a.y;
-      rv[0] = c.x; rv[1] = c.y;
+      pv[0] = na.x; pv[1] = na.y;
+      rv[0] = nc.x; rv[1] = nc.y;
+    }
+    const int64_t sn = s + tw;
+    if (sn < sr.end) {
+      const int64_t in = sn * Gm::RW + rr;
+      const int64_t offn = (in < n ? in : n - 1) * K + c0;
+      na = *reinterpret_cast<const T2*>(Pm + offn);
+      nc = *reinterpret_cast<const T2*>(R + offn);
     }
     const T *ps = nullptr, *ns = nullptr;
     if constexpr (Gm::NEED_LDS) {
@@ -393,7 +586,7 @@ bool dispatch_fast(const Plan& pl, F&& f) {
 }  // namespace
 
 bool fast_supported(const Plan& pl) {
-  if (std::getenv("BCG_GENERIC_ONLY")) return false;
+  if (std::getenv("BCG_GENERIC_ONLY") || pl.nnz < 1) return false;
   return dispatch_fast(pl, [](auto, auto) {});
 }
 

@@ -27,6 +27,7 @@ struct DevState {
 // thread plan of the block-product accumulation.
 struct Plan {
   int64_t n;
+  int64_t nnz;
   int k, p, q;
   int qo;       // packed blocks: 1 for the global subalgebra, q otherwise
   int global;   // 1: product summed over the q groups
@@ -45,7 +46,7 @@ struct Plan {
   int fast;     // 1: the k-specialised row kernels apply (k in {8..128}, p <= 16)
 };
 
-Plan make_plan(int64_t n, int k, int p, int global, int dec);
+Plan make_plan(int64_t n, int64_t nnz, int k, int p, int global, int dec);
 bool fast_supported(const Plan& pl);
 
 // ---- launchers (all enqueue on `s`; none synchronises) ----

@@ -433,43 +433,34 @@ __global__ __launch_bounds__(kBlock) void k_product(Plan pl, const T* __restrict
 // ------------------------------------------------------------------------
 
 // out[e] = sum over workgroups w of part[w][e], e < width, in a fixed order:
-// 16 row splits x 16 independent chains per entry, combined by fixed trees.
+// a block sums 16 entries, its 64 thread rows each take every 64th partial
+// (4 interleaved chains), and a fixed tree combines the 64 row sums.
 constexpr int kRedThreads = 1024;
 
 __global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict__ part, double* __restrict__ out,
                                                         int width, int W, int nwg, const DevState* st) {
   if (stopped(st)) return;
-  __shared__ double sh[16][64];
-  const int tid = threadIdx.x, lane = tid & 63, s = tid >> 6;  // s: split 0..15
-  const int e = blockIdx.x * 64 + lane;
-  double c[16];
-#pragma unroll
-  for (int u = 0; u < 16; ++u) c[u] = 0.0;
+  __shared__ double sh[64][16];
+  const int tid = threadIdx.x, le = tid & 15, s = tid >> 4;
+  const int e = blockIdx.x * 16 + le;
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
   if (e < width) {
-    // rows w = s + 16*m, chain u = m % 16
-    int m = 0;
-    for (; s + 16 * (m + 15) < nwg; m += 16) {
-#pragma unroll
-      for (int u = 0; u < 16; ++u) c[u] += part[(int64_t)(s + 16 * (m + u)) * W + e];
+    int w = s;
+    for (; w + 192 < nwg; w += 256) {
+      c0 += part[(int64_t)w * W + e];
+      c1 += part[(int64_t)(w + 64) * W + e];
+      c2 += part[(int64_t)(w + 128) * W + e];
+      c3 += part[(int64_t)(w + 192) * W + e];
     }
-    for (int u = 0; s + 16 * (m + u) < nwg; ++u) c[u] += part[(int64_t)(s + 16 * (m + u)) * W + e];
+    for (; w < nwg; w += 64) c0 += part[(int64_t)w * W + e];
   }
-#pragma unroll
-  for (int w = 8; w > 0; w >>= 1)
-#pragma unroll
-    for (int u = 0; u < w; ++u) c[u] = c[u] + c[u + w];
-  sh[s][lane] = c[0];
+  sh[s][le] = (c0 + c1) + (c2 + c3);
   __syncthreads();
-  if (s == 0 && e < width) {
-    double t[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) t[u] = sh[u][lane];
-#pragma unroll
-    for (int w = 8; w > 0; w >>= 1)
-#pragma unroll
-      for (int u = 0; u < w; ++u) t[u] = t[u] + t[u + w];
-    out[e] = t[0];
+  for (int h = 32; h > 0; h >>= 1) {
+    if (s < h) sh[s][le] = sh[s][le] + sh[s + h][le];
+    __syncthreads();
   }
+  if (s == 0 && e < width) out[e] = sh[0][le];
 }
 
 constexpr int kSmallLdsP = 48;  // p x p solves of up to this size run in LDS
@@ -710,7 +701,9 @@ __global__ __launch_bounds__(kBlock) void k_conv_beta(Plan pl, const double* __r
   }
 }
 
-// ---- one wave per p x p group (2 <= p <= 16): no workgroup barriers ----
+// ---- one wave per p x p group (p in {2, 4, 8, 16}), rows in registers ----
+// Lane i holds row i; the pivot row of each elimination step is broadcast
+// with readlane, so the factorisations need no LDS round trips or barriers.
 constexpr int kWaveP = 16;
 
 __device__ __forceinline__ void wsync() {
@@ -719,118 +712,131 @@ __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(v & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(v >> 32), l);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
 // lambda_g = sym(alpha_g)^{-1} rho_g by Cholesky (Algorithm 1 line 7).
-__global__ __launch_bounds__(kBlock) void k_solve_lambda_w(Plan pl, const double* __restrict__ alpha,
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_solve_lambda_r(Plan pl, const double* __restrict__ alpha,
                                                            const double* __restrict__ rho, double* __restrict__ lam,
                                                            float* __restrict__ lam32, DevState* st) {
   if (stopped(st)) return;
-  __shared__ double lds[4][2 * kWaveP * kWaveP];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, p = pl.p, pp = p * p;
+  __shared__ double Ls[4][P * P];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = blockIdx.x * 4 + wave;
   if (g >= pl.qo) return;
-  double* M = lds[wave];
-  double* Y = M + pp;
-  const double* al = alpha + (int64_t)g * pp;
-  const double* rh = rho + (int64_t)g * pp;
+  constexpr int PP = P * P;
+  const double* al = alpha + (int64_t)g * PP;
+  const double* rh = rho + (int64_t)g * PP;
+  const int i = lane < P ? lane : P - 1;
+  double a[P], L[P];
   bool bad = false;
-  for (int e = lane; e < pp; e += 64) {
-    const int i = e / p, j = e - i * p;
-    const double m = 0.5 * (al[i * p + j] + al[j * p + i]);
-    M[e] = m;
-    Y[e] = rh[e];
-    bad |= !isfinite(m) || !isfinite(rh[e]);
+#pragma unroll
+  for (int c = 0; c < P; ++c) {
+    a[c] = 0.5 * (al[i * P + c] + al[c * P + i]);
+    L[c] = 0.0;
+    bad |= !isfinite(a[c]) || !isfinite(rh[i * P + c]);
   }
   bad = __any(bad);
-  wsync();
-  for (int j = 0; j < p && !bad; ++j) {
-    const double ajj = M[j * p + j];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    if (bad) break;
+    double lj[P];
+#pragma unroll
+    for (int m = 0; m < j; ++m) lj[m] = readlane_d(L[m], j);
+    const double ajj = readlane_d(a[j], j);
     double sacc = 0.0;
-    for (int m = 0; m < j; ++m) sacc = fma(M[j * p + m], M[j * p + m], sacc);
+#pragma unroll
+    for (int m = 0; m < j; ++m) sacc = fma(lj[m], lj[m], sacc);
     const double d = ajj - sacc;
-    if (!isfinite(d) || !(d > p * DBL_EPSILON * ajj) || !(ajj > 0.0)) {
+    if (!isfinite(d) || !(d > P * DBL_EPSILON * ajj) || !(ajj > 0.0)) {
       bad = true;
       break;
     }
     const double ljj = sqrt(d);
-    wsync();
-    if (lane == j) M[j * p + j] = ljj;
-    if (lane > j && lane < p) {
-      double t = 0.0;
-      for (int m = 0; m < j; ++m) t = fma(M[lane * p + m], M[j * p + m], t);
-      M[lane * p + j] = (M[lane * p + j] - t) / ljj;
-    }
-    wsync();
+    double t = 0.0;
+#pragma unroll
+    for (int m = 0; m < j; ++m) t = fma(L[m], lj[m], t);
+    const double lij = (a[j] - t) / ljj;
+    L[j] = lane == j ? ljj : (lane > j ? lij : 0.0);
   }
   if (bad) {
     if (lane == 0) set_status(st, BCG_EBREAKDOWN);
     return;
   }
-  if (lane < p) {
-    const int c = lane;
-    for (int i = 0; i < p; ++i) {
-      double t = Y[i * p + c];
-      for (int m = 0; m < i; ++m) t -= M[i * p + m] * Y[m * p + c];
-      Y[i * p + c] = t / M[i * p + i];
-    }
-    for (int i = p - 1; i >= 0; --i) {
-      double t = Y[i * p + c];
-      for (int m = i + 1; m < p; ++m) t -= M[m * p + i] * Y[m * p + c];
-      Y[i * p + c] = t / M[i * p + i];
-    }
-  }
+  double* Lw = Ls[wave];
+  if (lane < P)
+#pragma unroll
+    for (int c = 0; c < P; ++c) Lw[lane * P + c] = L[c];
   wsync();
-  double* lo = lam + (int64_t)g * pp;
-  float* lo32 = lam32 + (int64_t)g * pp;
-  for (int e = lane; e < pp; e += 64) {
-    lo[e] = Y[e];
-    lo32[e] = static_cast<float>(Y[e]);
+  if (lane < P) {  // lane = right-hand-side column
+    const int c = lane;
+    double y[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) y[r] = rh[r * P + c];
+#pragma unroll
+    for (int r = 0; r < P; ++r) {  // L y = rho
+      double t = y[r];
+#pragma unroll
+      for (int m = 0; m < r; ++m) t -= Lw[r * P + m] * y[m];
+      y[r] = t / Lw[r * P + r];
+    }
+#pragma unroll
+    for (int r = P - 1; r >= 0; --r) {  // L^T x = y
+      double t = y[r];
+#pragma unroll
+      for (int m = r + 1; m < P; ++m) t -= Lw[m * P + r] * y[m];
+      y[r] = t / Lw[r * P + r];
+    }
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      lam[(int64_t)g * PP + r * P + c] = y[r];
+      lam32[(int64_t)g * PP + r * P + c] = static_cast<float>(y[r]);
+    }
   }
 }
 
-// Stop rule, then beta_g = rho_g^{-1} rho_new_g by LU with partial pivoting
-// (first largest magnitude on ties), one wave per group.
-__global__ __launch_bounds__(kBlock) void k_conv_beta_w(Plan pl, const double* __restrict__ red_new,
+// Stop rule (each wave decides redundantly, no workgroup barrier), then
+// beta_g = rho_g^{-1} rho_new_g by LU with partial pivoting: the largest
+// magnitude in the pivot column, the first (in the current row order) on ties.
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_conv_beta_r(Plan pl, const double* __restrict__ red_new,
                                                         const double* __restrict__ r0,
                                                         const double* __restrict__ rho_old, double* __restrict__ beta,
                                                         float* __restrict__ beta32, double* __restrict__ ratios,
                                                         DevState* st, double tol, int it, int maxit) {
   if (stopped(st)) return;
-  const int tid = threadIdx.x, k = pl.k, p = pl.p, pp = p * p;
-  __shared__ double smax[kBlock];
-  __shared__ int sbad[kBlock];
-  __shared__ double lds[4][2 * kWaveP * kWaveP];
+  __shared__ double Us[4][P * P];
+  __shared__ double Ys[4][P * P];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, k = pl.k;
   double mx = 0.0;
-  int bad = 0;
-  for (int j = tid; j < k; j += kBlock) {
+  bool badr = false;
+  for (int j = lane; j < k; j += 64) {
     const double c = red_new[pl.E + j];
     const double rr = r0[j];
     const double ratio = (rr == 0.0) ? 0.0 : sqrt(c) / rr;
     if (!isfinite(ratio))
-      bad = 1;
+      badr = true;
     else
       mx = fmax(mx, ratio);
-    if (blockIdx.x == 0) ratios[j] = ratio;
+    if (blockIdx.x == 0 && wave == 0) ratios[j] = ratio;
   }
-  smax[tid] = mx;
-  sbad[tid] = bad;
-  __syncthreads();
-  for (int s2 = kBlock / 2; s2 > 0; s2 >>= 1) {
-    if (tid < s2) {
-      smax[tid] = fmax(smax[tid], smax[tid + s2]);
-      sbad[tid] |= sbad[tid + s2];
-    }
-    __syncthreads();
-  }
-  const bool lead = blockIdx.x == 0 && tid == 0;
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+  badr = __any(badr);
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   if (lead) {
     st->iter = it;
-    st->max_ratio = sbad[0] ? NAN : smax[0];
+    st->max_ratio = badr ? NAN : mx;
   }
-  if (sbad[0]) {
+  if (badr) {
     if (lead) set_status(st, BCG_EBREAKDOWN);
     return;
   }
-  if (smax[0] <= tol) {
+  if (mx <= tol) {
     if (lead) set_status(st, BCG_OK);
     return;
   }
@@ -838,70 +844,106 @@ __global__ __launch_bounds__(kBlock) void k_conv_beta_w(Plan pl, const double* _
     if (lead) set_status(st, BCG_NOT_CONVERGED);
     return;
   }
-  const int wave = tid >> 6, lane = tid & 63;
   const int g = blockIdx.x * 4 + wave;
   if (g >= pl.qo) return;
-  double* M = lds[wave];
-  double* Y = M + pp;
+  constexpr int PP = P * P;
+  const int i = lane < P ? lane : P - 1;
+  double m[P], y[P];
   bool fail = false;
-  for (int e = lane; e < pp; e += 64) {
-    M[e] = rho_old[(int64_t)g * pp + e];
-    Y[e] = red_new[(int64_t)g * pp + e];
-    fail |= !isfinite(M[e]);
+#pragma unroll
+  for (int c = 0; c < P; ++c) {
+    m[c] = rho_old[(int64_t)g * PP + i * P + c];
+    y[c] = red_new[(int64_t)g * PP + i * P + c];
+    fail |= !isfinite(m[c]);
   }
   fail = __any(fail);
-  wsync();
-  for (int j = 0; j < p && !fail; ++j) {
-    // pivot: largest |M[i][j]|, i >= j, smallest i on ties
-    double v = (lane >= j && lane < p) ? fabs(M[lane * p + j]) : -1.0;
-    int idx = lane;
+  int pos = lane;  // current position of the row this lane holds
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    if (fail) break;
+    double v = (lane < P && pos >= j) ? fabs(m[j]) : -1.0;
+    int key = lane < P ? pos : 1 << 20;
+    int who = lane;
     for (int off = 32; off > 0; off >>= 1) {
       const double ov = __shfl_xor(v, off);
-      const int oi = __shfl_xor(idx, off);
-      if (ov > v || (ov == v && oi < idx)) {
+      const int ok2 = __shfl_xor(key, off);
+      const int ow = __shfl_xor(who, off);
+      if (ov > v || (ov == v && ok2 < key)) {
         v = ov;
-        idx = oi;
+        key = ok2;
+        who = ow;
       }
     }
-    if (v == 0.0) {
+    // lane 0's winner decides for the wave (all lanes agree unless a NaN
+    // reached the pivot column, which is a breakdown either way)
+    const double vu = readlane_d(v, 0);
+    if (!(vu > 0.0)) {
       fail = true;
       break;
     }
-    const int pr = idx;
-    if (pr != j) {
-      if (lane < p) {
-        double t = M[j * p + lane];
-        M[j * p + lane] = M[pr * p + lane];
-        M[pr * p + lane] = t;
-        t = Y[j * p + lane];
-        Y[j * p + lane] = Y[pr * p + lane];
-        Y[pr * p + lane] = t;
-      }
-      wsync();
+    const int pl_ = __builtin_amdgcn_readfirstlane(who);
+    const unsigned long long atj = __ballot(lane < P && pos == j);
+    const int la = __ffsll(static_cast<long long>(atj)) - 1;
+    const int pw = __builtin_amdgcn_readlane(pos, pl_);
+    if (lane == pl_)
+      pos = j;
+    else if (lane == la)
+      pos = pw;
+    double pr[P], py[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      pr[c] = c >= j ? readlane_d(m[c], pl_) : 0.0;
+      py[c] = readlane_d(y[c], pl_);
     }
-    if (lane > j && lane < p) {
-      const double l = M[lane * p + j] / M[j * p + j];
-      for (int c = j + 1; c < p; ++c) M[lane * p + c] -= l * M[j * p + c];
-      for (int c = 0; c < p; ++c) Y[lane * p + c] -= l * Y[j * p + c];
+    if (lane < P && pos > j) {
+      const double l = m[j] / pr[j];
+#pragma unroll
+      for (int c = j + 1; c < P; ++c) m[c] -= l * pr[c];
+#pragma unroll
+      for (int c = 0; c < P; ++c) y[c] -= l * py[c];
     }
-    wsync();
   }
   if (fail) {
     if (lane == 0) set_status(st, BCG_EBREAKDOWN);
     return;
   }
-  if (lane < p) {
+  double* U = Us[wave];
+  double* Yw = Ys[wave];
+  if (lane < P)
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      U[pos * P + c] = m[c];
+      Yw[pos * P + c] = y[c];
+    }
+  wsync();
+  if (lane < P) {
     const int c = lane;
-    for (int i = p - 1; i >= 0; --i) {
-      double t = Y[i * p + c];
-      for (int m2 = i + 1; m2 < p; ++m2) t -= M[i * p + m2] * Y[m2 * p + c];
-      Y[i * p + c] = t / M[i * p + i];
+    double x[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) x[r] = Yw[r * P + c];
+#pragma unroll
+    for (int r = P - 1; r >= 0; --r) {
+      double t = x[r];
+#pragma unroll
+      for (int mm = r + 1; mm < P; ++mm) t -= U[r * P + mm] * x[mm];
+      x[r] = t / U[r * P + r];
+    }
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      beta[(int64_t)g * PP + r * P + c] = x[r];
+      beta32[(int64_t)g * PP + r * P + c] = static_cast<float>(x[r]);
     }
   }
-  wsync();
-  for (int e = lane; e < pp; e += 64) {
-    beta[(int64_t)g * pp + e] = Y[e];
-    beta32[(int64_t)g * pp + e] = static_cast<float>(Y[e]);
+}
+
+template <typename F>
+bool dispatch_small_p(int p, F&& f) {
+  switch (p) {
+    case 2: f(std::integral_constant<int, 2>()); return true;
+    case 4: f(std::integral_constant<int, 4>()); return true;
+    case 8: f(std::integral_constant<int, 8>()); return true;
+    case 16: f(std::integral_constant<int, 16>()); return true;
+    default: return false;
   }
 }
 
@@ -958,9 +1000,10 @@ void dispatch_shape(const Plan& pl, F&& f) {
 
 }  // namespace
 
-Plan make_plan(int64_t n, int k, int p, int global, int dec) {
+Plan make_plan(int64_t n, int64_t nnz, int k, int p, int global, int dec) {
   Plan pl{};
   pl.n = n;
+  pl.nnz = nnz;
   pl.k = k;
   pl.p = p;
   pl.q = k / p;
@@ -1047,15 +1090,16 @@ void launch_product(const Plan& pl, const T* X, const T* Y, double* part, const 
 }
 
 void launch_reduce(const Plan& pl, const double* part, double* out, int width, const DevState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3((width + 63) / 64), dim3(kRedThreads), 0, s, part, out, width, pl.W, pl.nwg, st);
+  hipLaunchKernelGGL(k_reduce, dim3((width + 15) / 16), dim3(kRedThreads), 0, s, part, out, width, pl.W, pl.nwg, st);
 }
 
 void launch_solve_lambda(const Plan& pl, const double* alpha, const double* rho, double* lam, float* lam32,
                          double* ws, DevState* st, hipStream_t s) {
-  if (pl.p >= 2 && pl.p <= kWaveP) {
-    hipLaunchKernelGGL(k_solve_lambda_w, dim3((pl.qo + 3) / 4), dim3(kBlock), 0, s, pl, alpha, rho, lam, lam32, st);
+  if (dispatch_small_p(pl.p, [&](auto Pc) {
+        hipLaunchKernelGGL((k_solve_lambda_r<decltype(Pc)::value>), dim3((pl.qo + 3) / 4), dim3(kBlock), 0, s, pl,
+                           alpha, rho, lam, lam32, st);
+      }))
     return;
-  }
   const int grid = pl.p == 1 ? 1 : pl.qo;
   hipLaunchKernelGGL(k_solve_lambda, dim3(grid), dim3(kBlock), 0, s, pl, alpha, rho, lam, lam32, ws, st);
 }
@@ -1063,11 +1107,11 @@ void launch_solve_lambda(const Plan& pl, const double* alpha, const double* rho,
 void launch_conv_beta(const Plan& pl, const double* red_new, const double* r0, const double* rho_old, double* beta,
                       float* beta32, double* ws, double* ratios, DevState* st, double tol, int it, int maxit,
                       hipStream_t s) {
-  if (pl.p >= 2 && pl.p <= kWaveP) {
-    hipLaunchKernelGGL(k_conv_beta_w, dim3((pl.qo + 3) / 4), dim3(kBlock), 0, s, pl, red_new, r0, rho_old, beta,
-                       beta32, ratios, st, tol, it, maxit);
+  if (dispatch_small_p(pl.p, [&](auto Pc) {
+        hipLaunchKernelGGL((k_conv_beta_r<decltype(Pc)::value>), dim3((pl.qo + 3) / 4), dim3(kBlock), 0, s, pl,
+                           red_new, r0, rho_old, beta, beta32, ratios, st, tol, it, maxit);
+      }))
     return;
-  }
   const int grid = pl.p == 1 ? 1 : pl.qo;
   hipLaunchKernelGGL(k_conv_beta, dim3(grid), dim3(kBlock), 0, s, pl, red_new, r0, rho_old, beta, beta32, ws, ratios,
                      st, tol, it, maxit);

@@ -514,7 +514,7 @@ int bcg_create(const bcg_csr* A, int k, int subalgebra, int p, bcg_handle** out)
   h->p = pn;
   h->variant = subalgebra;
   const int dec = pn == 1 && (subalgebra == BCG_PARALLEL || subalgebra == BCG_HYBRID);
-  h->pl = make_plan(h->n, k, pn, subalgebra == BCG_GLOBAL ? 1 : 0, dec);
+  h->pl = make_plan(h->n, h->nnz, k, pn, subalgebra == BCG_GLOBAL ? 1 : 0, dec);
   if (const char* env = std::getenv("BCG_POLL_EVERY")) h->chunk = std::max(1, std::atoi(env));
   h->host_ratios.assign(k, 1.0);
   const Plan& pl = h->pl;
