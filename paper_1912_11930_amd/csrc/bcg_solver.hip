@@ -388,6 +388,18 @@ int solve_fp64(bcg_handle* h, const double* B, double* X, double tol, int maxit,
   return fin.status;
 }
 
+// Inner reduction target of a refinement step: the remaining factor
+// tol/ratio (with a factor 2 of margin) is split evenly over the fewest outer
+// steps that each need no more than inner_tol/4, so the last step does not
+// overshoot the stop rule by a full inner tolerance.
+double inner_target(double inner_tol, double tol, double ratio) {
+  const double need = 0.5 * tol / ratio;
+  if (!(need > 0.0) || need >= 1.0) return inner_tol;
+  const double floor_t = 0.25 * inner_tol;
+  const double m = std::max(1.0, std::ceil(std::log(need) / std::log(floor_t) - 1e-12));
+  return std::min(std::max(std::pow(need, 1.0 / m), floor_t), 0.5);
+}
+
 // Mixed precision: FP32 inner block CG, FP64 outer iterative refinement.
 int solve_refine(bcg_handle* h, const double* B, double* X, double tol, int maxit) {
   const Plan& pl = h->pl;
@@ -436,7 +448,8 @@ int solve_refine(bcg_handle* h, const double* B, double* X, double tol, int maxi
         IterBuffers<float> b{h->vals32, h->D32, h->R32, h->P32, h->Q32, h->lam32, h->beta32};
         h->fast_now = h->pl.fast;
         DevState fin{};
-        if ((rc = run_iterations<float>(h, b, h->inner_tol, h->inner_maxit, &fin))) return rc;
+        if ((rc = run_iterations<float>(h, b, inner_target(h->inner_tol, tol, ratio), h->inner_maxit, &fin)))
+          return rc;
         info.iterations += fin.iter;
         info.outer_iterations = outer;
         if (fin.status < 0) {

@@ -1,0 +1,152 @@
+"""FP32-bulk / FP64-refinement solves and the adjoint gradient, on the GPU.
+
+Refinement iterates depend on FP32 rounding order and are parity unpinned;
+what is checked is the final FP64 accuracy: the true residual recomputed on
+the CPU from the returned X, and the distance to an FP64 reference solution.
+Gradients are checked against the oracle's dense formula and, on the 512^2
+diffusion workload, against central finite differences in the coefficients.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import torch
+
+import oracle
+from oracle.bcg import solve as oracle_solve
+from oracle.grad import kappa_vjp as oracle_kappa_vjp, sampled_outer as oracle_sampled_outer
+from oracle.stencil import stencil_csr
+from tests.gpu_helpers import csr_to_dev, dev, host, log, rel
+from workload import WORKLOADS, cell_coefficients, fd_indices, loss_weights, rhs
+
+pytestmark = pytest.mark.gpu
+
+
+def _P():
+    import paper_1912_11930_amd as P
+    return P
+
+
+def _true_ratio(A, B, X):
+    R = B - A @ X
+    return float(np.max(np.linalg.norm(R, axis=0) / np.linalg.norm(B, axis=0)))
+
+
+@pytest.mark.parametrize("variant,p", [("block", 0), ("hybrid", 4), ("global", 1), ("parallel", 1), ("hybrid", 8)])
+def test_refine_reaches_fp64_accuracy(variant, p):
+    log(f"refine {variant} p={p}")
+    P = _P()
+    A = stencil_csr(3, 20, cell_coefficients(3, 20, 1.0))
+    B = rhs(A.shape[0], 16, "normal")
+    s = P.BCG(*csr_to_dev(A), k=16, subalgebra=variant, p=p)
+    s.set_precision("fp32_refine", inner_tol=1e-4, inner_maxit=2000)
+    tol = 1e-10
+    X, info = s.solve(dev(B), tol=tol)
+    Xh = host(X)
+    assert info["status"] == oracle.OK, info
+    assert info["outer_iterations"] >= 2
+    assert _true_ratio(A, B, Xh) <= tol
+    Xref = np.column_stack([spla.spsolve(A.tocsc(), B[:, j]) for j in range(B.shape[1])])
+    assert rel(Xh, Xref) <= 1e-7
+    # the FP64 solve to the same tolerance agrees just as well
+    s64 = P.BCG(*csr_to_dev(A), k=16, subalgebra=variant, p=p)
+    X64, i64 = s64.solve(dev(B), tol=tol)
+    assert rel(Xh, host(X64)) <= 1e-7
+
+
+def test_refine_stagnation_falls_back_to_fp64():
+    # an inner tolerance too loose to halve the residual per outer step
+    P = _P()
+    A = stencil_csr(2, 40, cell_coefficients(2, 40, 1.0))
+    B = rhs(A.shape[0], 8, "uniform")
+    s = P.BCG(*csr_to_dev(A), k=8, subalgebra="hybrid", p=4)
+    s.set_precision("fp32_refine", inner_tol=0.9, inner_maxit=1)
+    X, info = s.solve(dev(B), tol=1e-9)
+    assert info["status"] == oracle.OK
+    assert info["fp64_fallback"] == 1
+    assert _true_ratio(A, B, host(X)) <= 1e-8
+
+
+def test_refine_matches_oracle_refinement_accuracy():
+    # the oracle's own FP32/FP64 refinement reaches the same accuracy class
+    from oracle import refine
+    P = _P()
+    A = stencil_csr(2, 24, cell_coefficients(2, 24, 0.7))
+    B = rhs(A.shape[0], 8, "normal")
+    Xo, io = refine.solve(A, B, "hybrid", 4, tol=1e-10, inner_tol=1e-4, inner_maxit=2000)
+    s = P.BCG(*csr_to_dev(A), k=8, subalgebra="hybrid", p=4)
+    s.set_precision("fp32_refine", inner_tol=1e-4, inner_maxit=2000)
+    X, info = s.solve(dev(B), tol=1e-10)
+    assert io["status"] == info["status"] == oracle.OK
+    assert abs(io["outer_iterations"] - info["outer_iterations"]) <= 1
+    assert rel(host(X), Xo) <= 1e-7
+
+
+def test_sampled_outer_and_solve_gradient_dense():
+    P = _P()
+    dim, N, k = 2, 10, 3
+    kappa = cell_coefficients(dim, N, 0.5)
+    A = stencil_csr(dim, N, kappa)
+    B = rhs(A.shape[0], k, "normal")
+    W = loss_weights(A.shape[0], k)
+    kt = torch.tensor(kappa, dtype=torch.float64, device="cuda", requires_grad=True)
+    Bt = dev(B).requires_grad_(True)
+    rp, ci, _ = P.stencil(dim, N, kt.detach())
+    s = P.BCG(rp, ci, P.stencil(dim, N, kt.detach())[2], k=k, subalgebra="block")
+    vals = P.StencilValues.apply(kt, dim, N)
+    X = P.BCGSolve.apply(vals, Bt, s, 1e-12, 10000)
+    L = (dev(W) * X).sum()
+    L.backward()
+    Ad = A.toarray()
+    Xd = np.linalg.solve(Ad, B)
+    Yd = np.linalg.solve(Ad, W)
+    np.testing.assert_allclose(host(Bt.grad), Yd, rtol=0, atol=1e-10 * np.abs(Yd).max())
+    dvals = oracle_sampled_outer(A, Yd, Xd, -1.0)
+    dk = oracle_kappa_vjp(dim, N, kappa, A, dvals)
+    np.testing.assert_allclose(host(kt.grad), dk, rtol=0, atol=1e-9 * np.abs(dk).max())
+
+
+@pytest.mark.timeout(600)
+def test_fd_check_diffusion2d_512():
+    """Adjoint gradient vs central differences on 64 coefficients (512^2, k = 32).
+
+    Forward and adjoint solves at tol 1e-12; each +/- pair runs the
+    unperturbed iteration count + 5 in fixed-iteration mode (a smooth map);
+    the difference of the two solutions is formed before the loss sum.
+    Tolerance: 1e-5 * (|g| + max|g|). The difference quotient carries the
+    rounding noise of two ~700-iteration solves divided by 2h = 2e-6, about
+    3e-6 of the gradient's scale here, so a bound relative to each component
+    alone is not attainable for the small components; a wrong derivative
+    (sign, transpose, missing face) is off by O(1) of the scale.
+    """
+    P = _P()
+    w = WORKLOADS["diffusion2d_512_k32"]
+    dim, N, k = w.dim, w.N, w.k
+    h = w.extra["fd_step"]
+    kappa = cell_coefficients(dim, N, w.sigma)
+    B = dev(rhs(w.n, k, w.rhs))
+    W = dev(loss_weights(w.n, k))
+    kt = torch.tensor(kappa, dtype=torch.float64, device="cuda", requires_grad=True)
+    rp, ci, v0 = P.stencil(dim, N, kt.detach())
+    s = P.BCG(rp, ci, v0, k=k, subalgebra="block")
+    vals = P.StencilValues.apply(kt, dim, N)
+    X = P.BCGSolve.apply(vals, B, s, 1e-12, 100000)
+    its = s.info()["iterations"]
+    (W * X).sum().backward()
+    g_ad = host(kt.grad)
+    m = its + 5
+    idx = fd_indices(w.n, w.extra["fd_count"])
+    errs = []
+    gmax = np.abs(g_ad).max()
+    for c in idx:
+        kp = kt.detach().clone(); kp[c] += h
+        km = kt.detach().clone(); km[c] -= h
+        s.update_values(P.stencil(dim, N, kp)[2])
+        Xp, _ = s.solve(B, tol=0.0, maxit=m)
+        s.update_values(P.stencil(dim, N, km)[2])
+        Xm, _ = s.solve(B, tol=0.0, maxit=m)
+        g_fd = float((W * (Xp - Xm)).sum()) / (2 * h)
+        errs.append((c, g_fd, g_ad[c]))
+    worst = max(abs(a - b) / (abs(b) + gmax) for _, a, b in errs)
+    log(f"fd: iterations={its} gmax={gmax:.3e} worst |fd-ad|/(|ad|+max|ad|)={worst:.2e}")
+    for c, g_fd, g in errs:
+        assert abs(g_fd - g) <= 1e-5 * (abs(g) + gmax), (c, g_fd, g)
