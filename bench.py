@@ -69,6 +69,79 @@ def measured_traffic(kernel: str, workload: str, variant: str, precision: str):
     return rec.get("bytes_per_launch")
 
 
+KERNEL_NAMES = {"spmm": "k_spmm_fast", "update_xr": "k_update_xr_fast", "update_p": "k_update_p_fast"}
+COPY_BYTES = 2 << 30
+
+
+def copy_calibration() -> int:
+    """A plain device copy of COPY_BYTES (counter calibration for --traffic-from)."""
+    import torch
+    a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 3}), flush=True)
+    return 0
+
+
+def _pmc_means(db_path: str, counter: str) -> dict:
+    """Per-kernel mean counter value over dispatches that did work."""
+    import sqlite3
+    db = sqlite3.connect(db_path)
+    cols = [r[1] for r in db.execute("pragma table_info(counters_collection)")]
+    ci = {c: i for i, c in enumerate(cols)}
+    per = {}
+    for r in db.execute("select * from counters_collection"):
+        if r[ci["counter_name"]] != counter:
+            continue
+        per.setdefault(r[ci["kernel_name"]], []).append(float(r[ci["value"]]))
+    out = {}
+    for name, vals in per.items():
+        top = max(vals)
+        work = [v for v in vals if v > 0.01 * top]  # launches that returned at entry are dropped
+        out[name] = sum(work) / len(work)
+    return out
+
+
+def traffic_from(directory: str, workload: str, variant: str, precision: str) -> int:
+    """Write profiles/traffic.json from four rocprofv3 --pmc databases under
+    `directory`: copy_fetch, copy_write (bench.py --copy-calibration) and
+    fetch, write (the benchmark). FETCH_SIZE / WRITE_SIZE are KiB per dispatch;
+    each is scaled so that the plain copy reads and writes COPY_BYTES."""
+    import glob
+
+    def db(sub):
+        return glob.glob(os.path.join(directory, sub, "**", "*_results.db"), recursive=True)[0]
+
+    def copy_kib(sub, counter):
+        vals = _pmc_means(db(sub), counter)
+        return max(vals.values())
+
+    f_fetch = (COPY_BYTES / 1024) / copy_kib("copy_fetch", "FETCH_SIZE")
+    f_write = (COPY_BYTES / 1024) / copy_kib("copy_write", "WRITE_SIZE")
+    fetch = _pmc_means(db("fetch"), "FETCH_SIZE")
+    write = _pmc_means(db("write"), "WRITE_SIZE")
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    rec = json.load(open(path)) if os.path.exists(path) else {}
+    for cls, kname in KERNEL_NAMES.items():
+        fk = [v for n, v in fetch.items() if kname in n]
+        wk = [v for n, v in write.items() if kname in n]
+        if not fk or not wk:
+            continue
+        rd = fk[0] * 1024 * f_fetch
+        wr = wk[0] * 1024 * f_write
+        rec[f"{cls}/{workload}/{variant}/{precision}"] = {
+            "bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr,
+            "fetch_kib": fk[0], "write_kib": wk[0], "fetch_scale": f_fetch, "write_scale": f_write,
+            "kernel_hash": kernel_hash(),
+        }
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1, sort_keys=True)
+    print(json.dumps(rec, indent=1, sort_keys=True))
+    return 0
+
+
 def cpu_baseline(w, variant: str, p: int, gpu_iterations: int, budget_s: float):
     """Time the oracle's iterations on the full system; scale to the solve."""
     import numpy as np
@@ -116,12 +189,20 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 2 GiB device copy (counter calibration)")
+    ap.add_argument("--traffic-from", default=None,
+                    help="write profiles/traffic.json from rocprofv3 --pmc databases in this folder")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
+    if args.traffic_from:
+        return traffic_from(args.traffic_from, args.workload, args.variant, args.precision)
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
-        log("bench.py: only --gpus 1 is supported (single-GPU build; see DESIGN.md for the sharding design)")
+        log("bench.py: only --gpus 1 is supported; the library has no multi-GPU path")
         return 2
 
     import numpy as np
