@@ -40,10 +40,10 @@ def algorithmic_bytes(cls: str, n: int, nnz: int, k: int, precision: str) -> flo
     vb = 4 if precision == "fp32_refine" else 8
     if cls == "spmm":            # A (values + column index + row pointer), P read, Q written
         return vb * nnz + 4 * nnz + 4 * (n + 1) + 2 * vb * n * k
-    if cls == "update_xr":       # X, P, Q, R read; X, R written
-        return 6 * vb * n * k
-    if cls == "update_p":        # P, R read; P written
+    if cls == "update_r":        # Q, R read; R written
         return 3 * vb * n * k
+    if cls == "update_xp":       # X, P, R read; X, P written
+        return 5 * vb * n * k
     raise ValueError(cls)
 
 
@@ -69,7 +69,7 @@ def measured_traffic(kernel: str, workload: str, variant: str, precision: str):
     return rec.get("bytes_per_launch")
 
 
-KERNEL_NAMES = {"spmm": "k_spmm_fast", "update_xr": "k_update_xr_fast", "update_p": "k_update_p_fast"}
+KERNEL_NAMES = {"spmm": "k_spmm_fast", "update_r": "k_update_r_fast", "update_xp": "k_update_xp_fast"}
 COPY_BYTES = 2 << 30
 
 
@@ -189,6 +189,8 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--schedule", default="natural", choices=["tiled", "natural"],
+                    help="row order of the sparse product: 32x32 x-y tiles swept through z (3D), or natural")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (counter calibration)")
     ap.add_argument("--traffic-from", default=None,
@@ -220,6 +222,10 @@ def main() -> int:
     B = torch.from_numpy(rhs_for(w)).to(dev)
     n, k, nnz = w.n, w.k, w.nnz
     solver = P.BCG(rp, ci, va, k=k, subalgebra=args.variant, p=args.p)
+    schedule = "natural"
+    if args.schedule == "tiled" and w.dim == 3:
+        solver.set_row_schedule(P.stencil_schedule(w.dim, w.N, 32, device=dev))
+        schedule = "tiled 32x32 (x,y) swept through z"
     if args.precision != "fp64":
         solver.set_precision(args.precision)
     p_eff = {"block": k, "parallel": 1}.get(args.variant, args.p or 1)
@@ -238,7 +244,7 @@ def main() -> int:
             f"{info['solve_ms']:.1f} ms true_rel_res={info['true_rel_res']:.2e}")
     breakdown = solver.kernel_times()
     solver.set_profiling(False)
-    cand = {c: breakdown[c][1] for c in ("spmm", "update_xr", "update_p")}
+    cand = {c: breakdown[c][1] for c in ("spmm", "update_r", "update_xp")}
     dominant = max(cand, key=cand.get)
 
     # timed region: events only around the dominant kernel class
@@ -267,7 +273,7 @@ def main() -> int:
     kernels = {c: {"launches": breakdown[c][0], "total_ms": round(breakdown[c][1], 3),
                    "avg_us": round(1e3 * breakdown[c][1] / max(breakdown[c][0], 1), 2)}
                for c in _capi.KERNEL_CLASSES if breakdown[c][0]}
-    for c in ("spmm", "update_xr", "update_p"):
+    for c in ("spmm", "update_r", "update_xp"):
         if c in kernels:
             b = algorithmic_bytes(c, n, nnz, k, args.precision)
             kernels[c]["GBps"] = round(b / (kernels[c]["avg_us"] * 1e-6) / 1e9, 1)
@@ -287,7 +293,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": w.name, "grid": f"{w.N}^{w.dim}", "n": n, "nnz": nnz, "k": k,
                    "variant": args.variant, "p": p_eff, "precision": args.precision, "tol": tol,
-                   "rhs": w.rhs},
+                   "rhs": w.rhs, "row_schedule": schedule},
         "iterations": its[-1] if its else None,
         "true_rel_res": info["true_rel_res"] if info else None,
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": PEAK_HBM_GBS,

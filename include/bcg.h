@@ -164,6 +164,19 @@ int bcg_update_values(bcg_handle *h, const double *values);
  */
 int bcg_csr_outer(bcg_handle *h, const double *Y, const double *X, double alpha, double *out_vals);
 
+/*
+ * bcg_set_row_schedule -- optional processing order of the rows in the
+ * sparse product Q = A P (not in the paper: a cache-locality schedule; the
+ * paper observes the product's cache behaviour degrading for large k,
+ * Section 4). order: device int32[n], a permutation of 0..n-1, copied.
+ * Every row is computed exactly as before; only the order, and with it the
+ * reuse of gathered rows of P in cache, changes (and the rounding order of
+ * the partial alpha products). NULL restores the natural order. Entries
+ * outside [0, n) return BCG_EINVAL; the permutation property itself is the
+ * caller's contract. Synchronous.
+ */
+int bcg_set_row_schedule(bcg_handle *h, const int32_t *order);
+
 /* Copies the summary of the last solve into *info (host struct). */
 int bcg_get_info(const bcg_handle *h, bcg_info *info);
 
@@ -180,8 +193,8 @@ int bcg_get_column_ratios(const bcg_handle *h, double *ratios, int k);
  */
 enum {
   BCG_K_SPMM = 0,      /* Q = A P with the partial <<P, Q>>              */
-  BCG_K_UPDATE_XR = 1, /* X += P lambda, R -= Q lambda, <<R, R>>, norms  */
-  BCG_K_UPDATE_P = 2,  /* P = R + P beta with the partial <<P, R>>      */
+  BCG_K_UPDATE_R = 1,  /* R -= Q lambda with <<R, R>> and column norms   */
+  BCG_K_UPDATE_XP = 2, /* X += P lambda, P = R + P beta, partial <<P, R>> */
   BCG_K_REDUCE = 3,    /* fixed-order sums of the per-workgroup partials */
   BCG_K_SMALL = 4,     /* Cholesky / LU solves and the stop rule         */
   BCG_K_RESIDUAL = 5,  /* B - A X, FP32 start of a refinement step, X += s D */
@@ -226,6 +239,13 @@ int64_t bcg_stencil_nnz(int dim, int N);
  * ordered on hip_stream (NULL = null stream). */
 int bcg_stencil_build(int dim, int N, const double *kappa, int32_t *rowptr, int32_t *colind,
                       double *values, void *hip_stream);
+
+/* Row schedule for bcg_set_row_schedule on the stencil matrices: in 3D,
+ * x-y tiles of tile x tile cells in row-major tile order, each swept through
+ * all z planes (x fastest inside a tile), so the z-neighbours a row gathers
+ * were touched one plane earlier; in 2D the natural order. order: device
+ * int32[N^dim]. Stream-ordered. */
+int bcg_stencil_schedule(int dim, int N, int tile, int32_t *order, void *hip_stream);
 
 /* Transpose Jacobian of the stencil values with respect to kappa:
  * dkappa[c] = sum_e dvalues[e] * d values[e] / d kappa[c] (device arrays;

@@ -42,7 +42,7 @@ class KernelTime(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
-KERNEL_CLASSES = ["spmm", "update_xr", "update_p", "reduce", "small", "residual", "product"]
+KERNEL_CLASSES = ["spmm", "update_r", "update_xp", "reduce", "small", "residual", "product"]
 
 # (name, restype, argtypes) for every function declared in include/bcg.h
 SIGNATURES = [
@@ -59,12 +59,15 @@ SIGNATURES = [
                                      ctypes.c_void_p]),
     ("bcg_get_info", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
     ("bcg_get_column_ratios", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
+    ("bcg_set_row_schedule", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("bcg_set_profiling", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("bcg_get_kernel_times", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KernelTime), ctypes.c_int]),
     ("bcg_last_error", ctypes.c_char_p, []),
     ("bcg_stencil_nnz", ctypes.c_int64, [ctypes.c_int, ctypes.c_int]),
     ("bcg_stencil_build", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    ("bcg_stencil_schedule", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                            ctypes.c_void_p]),
     ("bcg_stencil_kappa_vjp", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p]),
 ]

@@ -301,24 +301,31 @@ __global__ __launch_bounds__(kBlock) void k_spmm_fast(Plan pl, const int32_t* __
   const StepRange sr = wave_steps(nsteps);
   const int64_t tw = sr.stride;
   const int64_t n = pl.n;
-  // rows past n (last step) use row n-1 for their loads and are discarded
+  // Schedule entry e = step*RW + rr names the row (natural order without a
+  // schedule); entries past n (last step) use entry n-1 for their loads and
+  // are discarded.
+  const int32_t* __restrict__ sched = pl.sched;
   auto row_of = [&](int64_t step) -> int64_t {
-    const int64_t i = step * Gm::RW + rr;
-    return i < n ? i : n - 1;
+    int64_t e = step * Gm::RW + rr;
+    e = e < n ? e : n - 1;
+    return sched ? static_cast<int64_t>(sched[e]) : e;
   };
   // all loads of the loop are unconditional (clamped rows and entries), so
-  // the compiler's load-counter waits are exact
+  // the compiler's load-counter waits are exact; the schedule is read three
+  // steps, the CSR range two steps and the index chunk one step ahead
   const int64_t last = sr.end > sr.first ? sr.end - 1 : sr.first;
   int64_t s = sr.first;
   RowIdx<T> cur;
+  int64_t cur_row = 0, row1 = 0, row2 = 0;
   int nj0 = 0, nj1 = 0;  // CSR range of step s + tw
   if (s < sr.end) {
-    const int64_t i = row_of(s);
-    cur.j0 = rowptr[i];
-    cur.j1 = rowptr[i + 1];
-    const int64_t i1 = row_of(min(s + tw, last));
-    nj0 = rowptr[i1];
-    nj1 = rowptr[i1 + 1];
+    cur_row = row_of(s);
+    row1 = row_of(min(s + tw, last));
+    row2 = row_of(min(s + 2 * tw, last));
+    cur.j0 = rowptr[cur_row];
+    cur.j1 = rowptr[cur_row + 1];
+    nj0 = rowptr[row1];
+    nj1 = rowptr[row1 + 1];
     if constexpr (Gm::G <= 32) {
       CoopIdx<T, Gm::G> ci;
       ci.load(colind, vals, cur.j0, cur.j1, cg);
@@ -328,14 +335,13 @@ __global__ __launch_bounds__(kBlock) void k_spmm_fast(Plan pl, const int32_t* __
     }
   }
   for (; s < sr.end; s += tw) {
-    const int64_t i = s * Gm::RW + rr;
-    const bool ok = i < n;
-    const int64_t ic = ok ? i : n - 1;
+    const bool ok = s * Gm::RW + rr < n;
+    const int64_t i = cur_row;
     // 1. gathers of the current step and its own row of P
     T2 xv[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) xv[u] = *reinterpret_cast<const T2*>(Pm + (int64_t)cur.cols[u] * K + c0);
-    const T2 pv = *reinterpret_cast<const T2*>(Pm + ic * K + c0);
+    const T2 pv = *reinterpret_cast<const T2*>(Pm + i * K + c0);
     // 2. index chunk of the next step (CSR range already loaded)
     RowIdx<T> nxt;
     nxt.j0 = nj0;
@@ -345,10 +351,10 @@ __global__ __launch_bounds__(kBlock) void k_spmm_fast(Plan pl, const int32_t* __
       cnx.load(colind, vals, nj0, nj1, cg);
     else
       load_idx(nxt, colind, vals, nj0);
-    // 3. CSR range two steps ahead
-    const int64_t i2 = row_of(min(s + 2 * tw, last));
-    nj0 = rowptr[i2];
-    nj1 = rowptr[i2 + 1];
+    // 3. CSR range two steps ahead, schedule entry three steps ahead
+    nj0 = rowptr[row2];
+    nj1 = rowptr[row2 + 1];
+    const int64_t row3 = row_of(min(s + 3 * tw, last));
     // 4. consume the gathers
     T q[2] = {T(0), T(0)};
     {
@@ -396,20 +402,24 @@ __global__ __launch_bounds__(kBlock) void k_spmm_fast(Plan pl, const int32_t* __
     if constexpr (Gm::NEED_LDS) wave_sync();
     if constexpr (Gm::G <= 32) cnx.spread(nxt);
     cur = nxt;
+    cur_row = row1;
+    row1 = row2;
+    row2 = row3;
   }
   finish_partial<K, P, false>(acc, H, part + (int64_t)blockIdx.x * pl.W, pl);
 }
 
-// ------------------------------------------------------ X, R update
+// ------------------------------------------------------------ R update
+// R -= Q lambda (line 9) with the partial <<R, R>> (line 11) and the column
+// norms of the stop rule. X is updated later, in the pass that reads P anyway.
 template <typename T, int K, int P>
-__global__ __launch_bounds__(kBlock) void k_update_xr_fast(Plan pl, T* __restrict__ X, T* __restrict__ R,
-                                                           const T* __restrict__ Pm, const T* __restrict__ Q,
-                                                           const T* __restrict__ lam, double* __restrict__ part,
-                                                           const DevState* st) {
+__global__ __launch_bounds__(kBlock) void k_update_r_fast(Plan pl, T* __restrict__ R, const T* __restrict__ Q,
+                                                          const T* __restrict__ lam, double* __restrict__ part,
+                                                          const DevState* st) {
   if (fstopped(st)) return;
   using Gm = Geo<K, P>;
   using T2 = typename V2<T>::type;
-  __shared__ T slab[4][3][Gm::NEED_LDS ? Gm::SLAB : 1];
+  __shared__ T slab[4][2][Gm::NEED_LDS ? Gm::SLAB : 1];
   __shared__ double H[K * P + K];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int rr = lane / Gm::G, cg = lane - rr * Gm::G, c0 = 2 * cg;
@@ -424,63 +434,47 @@ __global__ __launch_bounds__(kBlock) void k_update_xr_fast(Plan pl, T* __restric
   const int64_t n = pl.n;
   int64_t s = sr.first;
   // operands of the next row step are loaded before the current one is used
-  T2 na{}, nb{}, nc{}, nd{};
+  T2 nb{}, nc{};
   if (s < sr.end) {
     const int64_t i = s * Gm::RW + rr;
     const int64_t off = (i < n ? i : n - 1) * K + c0;
-    na = *reinterpret_cast<const T2*>(Pm + off);
     nb = *reinterpret_cast<const T2*>(Q + off);
     nc = *reinterpret_cast<const T2*>(R + off);
-    nd = *reinterpret_cast<const T2*>(X + off);
   }
   for (; s < sr.end; s += tw) {
     const int64_t i = s * Gm::RW + rr;
     const bool ok = i < n;
     const int64_t off = i * K + c0;
-    T pv[2] = {T(0), T(0)}, qv[2] = {T(0), T(0)}, rv[2] = {T(0), T(0)}, xv[2] = {T(0), T(0)};
+    T qv[2] = {T(0), T(0)}, rv[2] = {T(0), T(0)};
     if (ok) {
-      pv[0] = na.x; pv[1] = na.y;
       qv[0] = nb.x; qv[1] = nb.y;
       rv[0] = nc.x; rv[1] = nc.y;
-      xv[0] = nd.x; xv[1] = nd.y;
     }
     const int64_t sn = s + tw;
     if (sn < sr.end) {
       const int64_t in = sn * Gm::RW + rr;
       const int64_t offn = (in < n ? in : n - 1) * K + c0;
-      na = *reinterpret_cast<const T2*>(Pm + offn);
       nb = *reinterpret_cast<const T2*>(Q + offn);
       nc = *reinterpret_cast<const T2*>(R + offn);
-      nd = *reinterpret_cast<const T2*>(X + offn);
     }
-    const T *ps = nullptr, *qs = nullptr, *rs = nullptr;
+    const T *qs = nullptr, *rs = nullptr;
     if constexpr (Gm::NEED_LDS) {
-      T* sp = slab[wave][0];
-      T* sq = slab[wave][1];
-      *reinterpret_cast<T2*>(sp + rr * K + c0) = T2{pv[0], pv[1]};
+      T* sq = slab[wave][0];
       *reinterpret_cast<T2*>(sq + rr * K + c0) = T2{qv[0], qv[1]};
       wave_sync();
-      ps = sp + rr * K + gcol;
       qs = sq + rr * K + gcol;
     }
-    T dx[2], dr[2];
-    apply_row<T, P>(dx, ps, pv, cf);
+    T dr[2];
     apply_row<T, P>(dr, qs, qv, cf);
     T rn[2];
 #pragma unroll
-    for (int v = 0; v < 2; ++v) {
-      xv[v] = xv[v] + dx[v];   // X + P lambda
-      rn[v] = rv[v] - dr[v];   // R - Q lambda
-    }
-    if (ok) {
-      *reinterpret_cast<T2*>(X + off) = T2{xv[0], xv[1]};
-      *reinterpret_cast<T2*>(R + off) = T2{rn[0], rn[1]};
-    }
+    for (int v = 0; v < 2; ++v) rn[v] = rv[v] - dr[v];  // R - Q lambda
+    if (ok) *reinterpret_cast<T2*>(R + off) = T2{rn[0], rn[1]};
     if constexpr (Gm::NEED_LDS) {
-      T* sr = slab[wave][2];
-      *reinterpret_cast<T2*>(sr + rr * K + c0) = T2{rn[0], rn[1]};
+      T* sr2 = slab[wave][1];
+      *reinterpret_cast<T2*>(sr2 + rr * K + c0) = T2{rn[0], rn[1]};
       wave_sync();
-      rs = sr + rr * K + gcol;
+      rs = sr2 + rr * K + gcol;
     }
     acc_row<T, P>(acc, rs, rn, rn);  // <<R, R>>
 #pragma unroll
@@ -490,12 +484,18 @@ __global__ __launch_bounds__(kBlock) void k_update_xr_fast(Plan pl, T* __restric
   finish_partial<K, P, true>(acc, H, part + (int64_t)blockIdx.x * pl.W, pl);
 }
 
-// ------------------------------------------------------------ P update
+// ------------------------------------------------------- X and P update
+// X += P lambda (line 8) and, unless this is the last iteration, P = R + P
+// beta (line 13) with the partial rho = <<P_new, R>> of the next line 6. On
+// the last iteration (stop rule met, iteration cap, breakdown after line 9)
+// only X is updated.
 template <typename T, int K, int P>
-__global__ __launch_bounds__(kBlock) void k_update_p_fast(Plan pl, T* __restrict__ Pm, const T* __restrict__ R,
-                                                          const T* __restrict__ beta, double* __restrict__ part,
-                                                          const DevState* st) {
+__global__ __launch_bounds__(kBlock) void k_update_xp_fast(Plan pl, T* __restrict__ X, T* __restrict__ Pm,
+                                                           const T* __restrict__ R, const T* __restrict__ lam,
+                                                           const T* __restrict__ beta, double* __restrict__ part,
+                                                           const DevState* st) {
   if (fstopped(st)) return;
+  const bool last = *reinterpret_cast<const volatile int*>(&st->last) != 0;
   using Gm = Geo<K, P>;
   using T2 = typename V2<T>::type;
   __shared__ T slab[4][2][Gm::NEED_LDS ? Gm::SLAB : 1];
@@ -503,8 +503,9 @@ __global__ __launch_bounds__(kBlock) void k_update_p_fast(Plan pl, T* __restrict
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int rr = lane / Gm::G, cg = lane - rr * Gm::G, c0 = 2 * cg;
   const int gcol = (c0 / P) * P;
-  T cf[2][P];
-  load_coeff<T, P>(cf, beta, c0, pl.global);
+  T cl[2][P], cb[2][P];
+  load_coeff<T, P>(cl, lam, c0, pl.global);
+  if (!last) load_coeff<T, P>(cb, beta, c0, pl.global);
   LaneAcc<P> acc;
   acc.zero();
   const int64_t nsteps = (pl.n + Gm::RW - 1) / Gm::RW;
@@ -512,21 +513,23 @@ __global__ __launch_bounds__(kBlock) void k_update_p_fast(Plan pl, T* __restrict
   const int64_t tw = sr.stride;
   const int64_t n = pl.n;
   int64_t s = sr.first;
-  T2 na{}, nc{};
+  T2 na{}, nc{}, nd{};
   if (s < sr.end) {
     const int64_t i = s * Gm::RW + rr;
     const int64_t off = (i < n ? i : n - 1) * K + c0;
     na = *reinterpret_cast<const T2*>(Pm + off);
     nc = *reinterpret_cast<const T2*>(R + off);
+    nd = *reinterpret_cast<const T2*>(X + off);
   }
   for (; s < sr.end; s += tw) {
     const int64_t i = s * Gm::RW + rr;
     const bool ok = i < n;
     const int64_t off = i * K + c0;
-    T pv[2] = {T(0), T(0)}, rv[2] = {T(0), T(0)};
+    T pv[2] = {T(0), T(0)}, rv[2] = {T(0), T(0)}, xv[2] = {T(0), T(0)};
     if (ok) {
       pv[0] = na.x; pv[1] = na.y;
       rv[0] = nc.x; rv[1] = nc.y;
+      xv[0] = nd.x; xv[1] = nd.y;
     }
     const int64_t sn = s + tw;
     if (sn < sr.end) {
@@ -534,6 +537,7 @@ __global__ __launch_bounds__(kBlock) void k_update_p_fast(Plan pl, T* __restrict
       const int64_t offn = (in < n ? in : n - 1) * K + c0;
       na = *reinterpret_cast<const T2*>(Pm + offn);
       nc = *reinterpret_cast<const T2*>(R + offn);
+      nd = *reinterpret_cast<const T2*>(X + offn);
     }
     const T *ps = nullptr, *ns = nullptr;
     if constexpr (Gm::NEED_LDS) {
@@ -542,19 +546,26 @@ __global__ __launch_bounds__(kBlock) void k_update_p_fast(Plan pl, T* __restrict
       wave_sync();
       ps = sp + rr * K + gcol;
     }
-    T dp[2];
-    apply_row<T, P>(dp, ps, pv, cf);
-    T pn[2];
+    T dx[2];
+    apply_row<T, P>(dx, ps, pv, cl);
 #pragma unroll
-    for (int v = 0; v < 2; ++v) pn[v] = rv[v] + dp[v];  // R + P beta
-    if (ok) *reinterpret_cast<T2*>(Pm + off) = T2{pn[0], pn[1]};
-    if constexpr (Gm::NEED_LDS) {
-      T* sn = slab[wave][1];
-      *reinterpret_cast<T2*>(sn + rr * K + c0) = T2{pn[0], pn[1]};
-      wave_sync();
-      ns = sn + rr * K + gcol;
+    for (int v = 0; v < 2; ++v) xv[v] = xv[v] + dx[v];  // X + P lambda
+    if (ok) *reinterpret_cast<T2*>(X + off) = T2{xv[0], xv[1]};
+    if (!last) {
+      T dp[2];
+      apply_row<T, P>(dp, ps, pv, cb);
+      T pn[2];
+#pragma unroll
+      for (int v = 0; v < 2; ++v) pn[v] = rv[v] + dp[v];  // R + P beta
+      if (ok) *reinterpret_cast<T2*>(Pm + off) = T2{pn[0], pn[1]};
+      if constexpr (Gm::NEED_LDS) {
+        T* sn2 = slab[wave][1];
+        *reinterpret_cast<T2*>(sn2 + rr * K + c0) = T2{pn[0], pn[1]};
+        wave_sync();
+        ns = sn2 + rr * K + gcol;
+      }
+      acc_row<T, P>(acc, ns, pn, rv);  // rho = <<P_new, R>>: a over P_new, b over R
     }
-    acc_row<T, P>(acc, ns, pn, rv);  // rho = <<P_new, R>>: a over P_new, b over R
     if constexpr (Gm::NEED_LDS) wave_sync();
   }
   finish_partial<K, P, false>(acc, H, part + (int64_t)blockIdx.x * pl.W, pl);
@@ -600,29 +611,30 @@ void launch_spmm_fast(const Plan& pl, const int32_t* rowptr, const int32_t* coli
 }
 
 template <typename T>
-void launch_update_xr_fast(const Plan& pl, T* X, T* R, const T* P, const T* Q, const T* lam, double* part,
-                           const DevState* st, hipStream_t s) {
+void launch_update_r_fast(const Plan& pl, T* R, const T* Q, const T* lam, double* part, const DevState* st,
+                          hipStream_t s) {
   dispatch_fast(pl, [&](auto Kc, auto Pc) {
-    hipLaunchKernelGGL((k_update_xr_fast<T, decltype(Kc)::value, decltype(Pc)::value>), dim3(pl.nwg), dim3(kBlock),
-                       0, s, pl, X, R, P, Q, lam, part, st);
+    hipLaunchKernelGGL((k_update_r_fast<T, decltype(Kc)::value, decltype(Pc)::value>), dim3(pl.nwg), dim3(kBlock), 0,
+                       s, pl, R, Q, lam, part, st);
   });
 }
 
 template <typename T>
-void launch_update_p_fast(const Plan& pl, T* P, const T* R, const T* beta, double* part, const DevState* st,
-                          hipStream_t s) {
+void launch_update_xp_fast(const Plan& pl, T* X, T* P, const T* R, const T* lam, const T* beta, double* part,
+                           const DevState* st, hipStream_t s) {
   dispatch_fast(pl, [&](auto Kc, auto Pc) {
-    hipLaunchKernelGGL((k_update_p_fast<T, decltype(Kc)::value, decltype(Pc)::value>), dim3(pl.nwg), dim3(kBlock), 0,
-                       s, pl, P, R, beta, part, st);
+    hipLaunchKernelGGL((k_update_xp_fast<T, decltype(Kc)::value, decltype(Pc)::value>), dim3(pl.nwg), dim3(kBlock),
+                       0, s, pl, X, P, R, lam, beta, part, st);
   });
 }
 
 #define BCG_FAST_INST(T)                                                                                           \
   template void launch_spmm_fast<T>(const Plan&, const int32_t*, const int32_t*, const T*, const T*, T*, double*, \
                                     const DevState*, hipStream_t);                                                 \
-  template void launch_update_xr_fast<T>(const Plan&, T*, T*, const T*, const T*, const T*, double*,              \
-                                         const DevState*, hipStream_t);                                            \
-  template void launch_update_p_fast<T>(const Plan&, T*, const T*, const T*, double*, const DevState*, hipStream_t);
+  template void launch_update_r_fast<T>(const Plan&, T*, const T*, const T*, double*, const DevState*,            \
+                                        hipStream_t);                                                              \
+  template void launch_update_xp_fast<T>(const Plan&, T*, T*, const T*, const T*, const T*, double*,              \
+                                         const DevState*, hipStream_t);
 BCG_FAST_INST(double)
 BCG_FAST_INST(float)
 

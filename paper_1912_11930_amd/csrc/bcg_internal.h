@@ -14,12 +14,14 @@ constexpr int kNabMax = 8;         // entry blocks per thread in fused products
 constexpr int kLamLds = 2048;      // coefficient entries kept in LDS
 
 // Device-side solve state. Every per-iteration kernel returns at entry once
-// `done` is set, which freezes X at the iterate the stop rule accepted.
+// `done` is set. `last` marks the final iteration (stop rule met, iteration
+// cap, breakdown after the residual update): its X/P pass then applies only
+// X += P lambda, and the reduction after it sets `done`.
 struct DevState {
   int done;
   int status;
   int iter;
-  int pad;
+  int last;
   double max_ratio;  // largest column ratio ||R_j|| / r0_j after the last iteration
 };
 
@@ -44,6 +46,7 @@ struct Plan {
   int64_t ntiles;
   int nwg;      // workgroups of the row kernels
   int fast;     // 1: the k-specialised row kernels apply (k in {8..128}, p <= 16)
+  const int32_t* sched;  // processing order of the sparse-product rows (nullptr: natural)
 };
 
 Plan make_plan(int64_t n, int64_t nnz, int k, int p, int global, int dec);
@@ -62,16 +65,18 @@ template <typename T>
 void launch_spmm_product(const Plan& pl, const int32_t* rowptr, const int32_t* colind, const T* vals,
                          const T* P, T* Q, double* part, const DevState* st, hipStream_t s);
 template <typename T>
-void launch_update_xr(const Plan& pl, T* X, T* R, const T* P, const T* Q, const T* lam, double* part,
-                      const DevState* st, hipStream_t s);
-template <typename T>
-void launch_update_p(const Plan& pl, T* P, const T* R, const T* beta, double* part, const DevState* st,
+void launch_update_r(const Plan& pl, T* R, const T* Q, const T* lam, double* part, const DevState* st,
                      hipStream_t s);
+template <typename T>
+void launch_update_xp(const Plan& pl, T* X, T* P, const T* R, const T* lam, const T* beta, double* part,
+                      const DevState* st, hipStream_t s);
 // stand-alone product for plans whose products do not fit the fused path
 template <typename T>
 void launch_product(const Plan& pl, const T* X, const T* Y, double* part, const DevState* st, hipStream_t s);
-void launch_reduce(const Plan& pl, const double* part, double* out, int width, const DevState* st,
-                   hipStream_t s);
+// finalize: the reduction after the X/P pass; on the last iteration it sets
+// `done` instead of reducing.
+void launch_reduce(const Plan& pl, const double* part, double* out, int width, DevState* st, hipStream_t s,
+                   int finalize = 0);
 void launch_solve_lambda(const Plan& pl, const double* alpha, const double* rho, double* lam, float* lam32,
                          double* ws, DevState* st, hipStream_t s);
 void launch_conv_beta(const Plan& pl, const double* red_new, const double* r0, const double* rho_old,
@@ -81,15 +86,16 @@ void launch_axpy_scaled(int64_t count, double* X, const float* D, const double* 
 void launch_sampled_outer(int64_t n, int k, const int32_t* rowptr, const int32_t* colind, const double* Y,
                           const double* X, double alpha, double* out, hipStream_t s);
 void launch_cast_values(int64_t nnz, const double* v, float* v32, hipStream_t s);
+void launch_check_range(const int32_t* order, int64_t n, int* flag, hipStream_t s);
 // k-specialised row kernels (16-byte aligned block vectors; see fast_supported)
 template <typename T>
 void launch_spmm_fast(const Plan& pl, const int32_t* rowptr, const int32_t* colind, const T* vals, const T* P,
                       T* Q, double* part, const DevState* st, hipStream_t s);
 template <typename T>
-void launch_update_xr_fast(const Plan& pl, T* X, T* R, const T* P, const T* Q, const T* lam, double* part,
-                           const DevState* st, hipStream_t s);
-template <typename T>
-void launch_update_p_fast(const Plan& pl, T* P, const T* R, const T* beta, double* part, const DevState* st,
+void launch_update_r_fast(const Plan& pl, T* R, const T* Q, const T* lam, double* part, const DevState* st,
                           hipStream_t s);
+template <typename T>
+void launch_update_xp_fast(const Plan& pl, T* X, T* P, const T* R, const T* lam, const T* beta, double* part,
+                           const DevState* st, hipStream_t s);
 
 }  // namespace bcg

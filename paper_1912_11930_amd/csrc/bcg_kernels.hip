@@ -1,13 +1,14 @@
 // Block CG kernels for gfx950 (generic path).
 //
-// One iteration of Algorithm 1 (Section 3, M = I) is five row-parallel passes
-// over the n x k block vectors (row-major, k fastest) plus small reductions
-// and solves:
+// One iteration of Algorithm 1 (Section 3, M = I) is three row-parallel
+// passes over the n x k block vectors (row-major, k fastest) plus small
+// reductions and solves:
 //   spmm_product : Q = A P                      and partial alpha = <<P, Q>>_S
 //   solve_lambda : lambda = sym(alpha)^{-1} rho  (Cholesky per group)
-//   update_xr    : X += P lambda, R -= Q lambda  and partial <<R, R>>_S, ||R_j||^2
+//   update_r     : R -= Q lambda                and partial <<R, R>>_S, ||R_j||^2
 //   conv_beta    : stop rule, beta = rho^{-1} rho_new (LU with partial pivoting)
-//   update_p     : P = R + P beta               and partial rho = <<P, R>>_S
+//   update_xp    : X += P lambda, P = R + P beta and partial rho = <<P, R>>_S
+// (X is updated in the pass that reads P anyway, one kernel after R),
 // so every block product is accumulated by the kernel that produces its
 // operands (the paper notes the recomputed rho can share a reduction with the
 // product before it, Section 3). The partial products of each workgroup are
@@ -34,6 +35,13 @@ __device__ __forceinline__ bool stopped(const DevState* st) {
 __device__ __forceinline__ void set_status(DevState* st, int status) {
   *reinterpret_cast<volatile int*>(&st->status) = status;
   *reinterpret_cast<volatile int*>(&st->done) = 1;
+}
+
+// The iteration that just updated R is the last one: X still receives its
+// P lambda in the X/P pass.
+__device__ __forceinline__ void set_last(DevState* st, int status) {
+  *reinterpret_cast<volatile int*>(&st->status) = status;
+  *reinterpret_cast<volatile int*>(&st->last) = 1;
 }
 
 // ------------------------------------------------------------------------
@@ -291,13 +299,13 @@ __global__ __launch_bounds__(kBlock) void k_spmm_product(Plan pl, const int32_t*
     const TileRange tr = tile_range(pl, t);
     for (int e = tid; e < tr.ne; e += kBlock) {
       const int r = e / k, c = e - r * k;
-      const int64_t i = tr.row0 + r;
+      const int64_t i = pl.sched ? static_cast<int64_t>(pl.sched[tr.row0 + r]) : tr.row0 + r;
       T s = T(0);
       const int j1 = rowptr[i + 1];
       for (int j = rowptr[i]; j < j1; ++j) s = fma(vals[j], P[(int64_t)colind[j] * k + c], s);
-      Q[tr.base + e] = s;
+      Q[i * k + c] = s;
       Qs[e] = s;
-      Ps[e] = P[tr.base + e];
+      Ps[e] = P[i * k + c];
     }
     __syncthreads();
     if (pl.fused) product_tile<T, RB, NAB>(acc, Ps, Qs, tr.rows, pl, tid, 0, pl.EB);
@@ -306,14 +314,12 @@ __global__ __launch_bounds__(kBlock) void k_spmm_product(Plan pl, const int32_t*
   if (pl.fused) product_finish<RB, NAB>(acc, part + (int64_t)blockIdx.x * pl.W, pl, scratch, tid, 0, pl.EB);
 }
 
-// X += P lambda, R -= Q lambda; partial <<R, R>> and column norms of R.
+// R -= Q lambda (line 9); partial <<R, R>> and column norms of R.
 template <typename T, int RB, int NAB>
-__global__ __launch_bounds__(kBlock) void k_update_xr(Plan pl, T* __restrict__ X, T* __restrict__ R,
-                                                      const T* __restrict__ P, const T* __restrict__ Q,
-                                                      const T* __restrict__ lam, double* __restrict__ part,
-                                                      const DevState* st) {
+__global__ __launch_bounds__(kBlock) void k_update_r(Plan pl, T* __restrict__ R, const T* __restrict__ Q,
+                                                     const T* __restrict__ lam, double* __restrict__ part,
+                                                     const DevState* st) {
   if (stopped(st)) return;
-  __shared__ T Ps[kTileElems];
   __shared__ T Qs[kTileElems];
   __shared__ T Rs[kTileElems];
   __shared__ T lamS[kLamLds];
@@ -328,24 +334,15 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(Plan pl, T* __restrict__ X
   double nacc = 0.0;
   for (int64_t t = blockIdx.x; t < pl.ntiles; t += gridDim.x) {
     const TileRange tr = tile_range(pl, t);
-    for (int e = tid; e < tr.ne; e += kBlock) {
-      Ps[e] = P[tr.base + e];
-      Qs[e] = Q[tr.base + e];
-    }
+    for (int e = tid; e < tr.ne; e += kBlock) Qs[e] = Q[tr.base + e];
     __syncthreads();
     for (int e = tid; e < tr.ne; e += kBlock) {
       const int r = e / k, c = e - r * k;
       const int g = c / p, b = c - g * p;
       const T* lg = L + (pl.global ? 0 : g * p * p) + b;
-      const T* pr = Ps + r * k + g * p;
       const T* qr = Qs + r * k + g * p;
-      T dx = T(0), dr = T(0);
-      for (int a = 0; a < p; ++a) {
-        const T l = lg[a * p];
-        dx = fma(pr[a], l, dx);
-        dr = fma(qr[a], l, dr);
-      }
-      X[tr.base + e] += dx;
+      T dr = T(0);
+      for (int a = 0; a < p; ++a) dr = fma(qr[a], lg[a * p], dr);
       const T rn = R[tr.base + e] - dr;
       R[tr.base + e] = rn;
       Rs[e] = rn;
@@ -360,44 +357,55 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(Plan pl, T* __restrict__ X
   norms_finish(nacc, prow + pl.E, k, scratch, tid);
 }
 
-// P = R + P beta; partial rho = <<P, R>> for the next iteration's line 6.
+// X += P lambda (line 8); unless last: P = R + P beta (line 13) and the
+// partial rho = <<P_new, R>> for the next iteration's line 6.
 template <typename T, int RB, int NAB>
-__global__ __launch_bounds__(kBlock) void k_update_p(Plan pl, T* __restrict__ P, const T* __restrict__ R,
-                                                     const T* __restrict__ beta, double* __restrict__ part,
-                                                     const DevState* st) {
+__global__ __launch_bounds__(kBlock) void k_update_xp(Plan pl, T* __restrict__ X, T* __restrict__ P,
+                                                      const T* __restrict__ R, const T* __restrict__ lam,
+                                                      const T* __restrict__ beta, double* __restrict__ part,
+                                                      const DevState* st) {
   if (stopped(st)) return;
+  const bool last = *reinterpret_cast<const volatile int*>(&st->last) != 0;
   __shared__ T Ps[kTileElems];
   __shared__ T Rs[kTileElems];
   __shared__ T Pn[kTileElems];
-  __shared__ T betaS[kLamLds];
+  __shared__ T cS[2 * kLamLds];
   __shared__ double scratch[kBlock * RB * RB];
   const int tid = threadIdx.x, k = pl.k, p = pl.p;
-  const bool lds_beta = pl.E <= kLamLds;
-  if (lds_beta)
-    for (int e = tid; e < pl.E; e += kBlock) betaS[e] = beta[e];
-  const T* L = lds_beta ? betaS : beta;
+  const bool lds_c = pl.E <= kLamLds;
+  if (lds_c)
+    for (int e = tid; e < pl.E; e += kBlock) {
+      cS[e] = lam[e];
+      if (!last) cS[kLamLds + e] = beta[e];
+    }
+  const T* L = lds_c ? cS : lam;
+  const T* Bt = lds_c ? cS + kLamLds : beta;
   Acc<RB, NAB> acc;
   acc.zero();
   for (int64_t t = blockIdx.x; t < pl.ntiles; t += gridDim.x) {
     const TileRange tr = tile_range(pl, t);
     for (int e = tid; e < tr.ne; e += kBlock) {
       Ps[e] = P[tr.base + e];
-      Rs[e] = R[tr.base + e];
+      if (!last) Rs[e] = R[tr.base + e];
     }
     __syncthreads();
     for (int e = tid; e < tr.ne; e += kBlock) {
       const int r = e / k, c = e - r * k;
       const int g = c / p, b = c - g * p;
-      const T* lg = L + (pl.global ? 0 : g * p * p) + b;
+      const int off = (pl.global ? 0 : g * p * p) + b;
       const T* pr = Ps + r * k + g * p;
-      T dp = T(0);
-      for (int a = 0; a < p; ++a) dp = fma(pr[a], lg[a * p], dp);
-      const T pn = Rs[e] + dp;
-      P[tr.base + e] = pn;
-      Pn[e] = pn;
+      T dx = T(0), dp = T(0);
+      for (int a = 0; a < p; ++a) dx = fma(pr[a], L[off + a * p], dx);
+      X[tr.base + e] += dx;
+      if (!last) {
+        for (int a = 0; a < p; ++a) dp = fma(pr[a], Bt[off + a * p], dp);
+        const T pn = Rs[e] + dp;
+        P[tr.base + e] = pn;
+        Pn[e] = pn;
+      }
     }
     __syncthreads();
-    if (pl.fused) product_tile<T, RB, NAB>(acc, Pn, Rs, tr.rows, pl, tid, 0, pl.EB);
+    if (pl.fused && !last) product_tile<T, RB, NAB>(acc, Pn, Rs, tr.rows, pl, tid, 0, pl.EB);
     __syncthreads();
   }
   if (pl.fused) product_finish<RB, NAB>(acc, part + (int64_t)blockIdx.x * pl.W, pl, scratch, tid, 0, pl.EB);
@@ -438,8 +446,12 @@ __global__ __launch_bounds__(kBlock) void k_product(Plan pl, const T* __restrict
 constexpr int kRedThreads = 1024;
 
 __global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict__ part, double* __restrict__ out,
-                                                        int width, int W, int nwg, const DevState* st) {
+                                                        int width, int W, int nwg, DevState* st, int finalize) {
   if (stopped(st)) return;
+  if (finalize && *reinterpret_cast<const volatile int*>(&st->last)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *reinterpret_cast<volatile int*>(&st->done) = 1;
+    return;
+  }
   __shared__ double sh[64][16];
   const int tid = threadIdx.x, le = tid & 15, s = tid >> 4;
   const int e = blockIdx.x * 16 + le;
@@ -598,15 +610,15 @@ __global__ __launch_bounds__(kBlock) void k_conv_beta(Plan pl, const double* __r
     st->max_ratio = sbad[0] ? NAN : smax[0];
   }
   if (sbad[0]) {
-    if (lead) set_status(st, BCG_EBREAKDOWN);
+    if (lead) set_last(st, BCG_EBREAKDOWN);
     return;
   }
   if (smax[0] <= tol) {
-    if (lead) set_status(st, BCG_OK);
+    if (lead) set_last(st, BCG_OK);
     return;
   }
   if (it >= maxit) {
-    if (lead) set_status(st, BCG_NOT_CONVERGED);
+    if (lead) set_last(st, BCG_NOT_CONVERGED);
     return;
   }
   if (tid == 0) flag = 0;
@@ -626,7 +638,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_beta(Plan pl, const double* __r
       beta32[e] = static_cast<float>(b);
     }
     __syncthreads();
-    if (tid == 0 && flag) set_status(st, BCG_EBREAKDOWN);
+    if (tid == 0 && flag) set_last(st, BCG_EBREAKDOWN);
     return;
   }
   __shared__ double lds[2 * kSmallLdsP * kSmallLdsP];
@@ -684,7 +696,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_beta(Plan pl, const double* __r
     __syncthreads();
   }
   if (flag) {
-    if (tid == 0) set_status(st, BCG_EBREAKDOWN);
+    if (tid == 0) set_last(st, BCG_EBREAKDOWN);
     return;
   }
   for (int c = tid; c < p; c += kBlock) {
@@ -833,15 +845,15 @@ __global__ __launch_bounds__(kBlock) void k_conv_beta_r(Plan pl, const double* _
     st->max_ratio = badr ? NAN : mx;
   }
   if (badr) {
-    if (lead) set_status(st, BCG_EBREAKDOWN);
+    if (lead) set_last(st, BCG_EBREAKDOWN);
     return;
   }
   if (mx <= tol) {
-    if (lead) set_status(st, BCG_OK);
+    if (lead) set_last(st, BCG_OK);
     return;
   }
   if (it >= maxit) {
-    if (lead) set_status(st, BCG_NOT_CONVERGED);
+    if (lead) set_last(st, BCG_NOT_CONVERGED);
     return;
   }
   const int g = blockIdx.x * 4 + wave;
@@ -904,7 +916,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_beta_r(Plan pl, const double* _
     }
   }
   if (fail) {
-    if (lane == 0) set_status(st, BCG_EBREAKDOWN);
+    if (lane == 0) set_last(st, BCG_EBREAKDOWN);
     return;
   }
   double* U = Us[wave];
@@ -998,7 +1010,22 @@ void dispatch_shape(const Plan& pl, F&& f) {
   }
 }
 
+// flag = 1 if any order[e] is outside [0, n).
+__global__ __launch_bounds__(kBlock) void k_check_range(const int32_t* __restrict__ order, int64_t n,
+                                                        int* __restrict__ flag) {
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock) {
+    const int32_t v = order[e];
+    if (v < 0 || v >= n) *reinterpret_cast<volatile int*>(flag) = 1;
+  }
+}
+
 }  // namespace
+
+void launch_check_range(const int32_t* order, int64_t n, int* flag, hipStream_t s) {
+  const int64_t blocks = (n + kBlock - 1) / kBlock;
+  const int grid = static_cast<int>(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096);
+  hipLaunchKernelGGL(k_check_range, dim3(grid), dim3(kBlock), 0, s, order, n, flag);
+}
 
 Plan make_plan(int64_t n, int64_t nnz, int k, int p, int global, int dec) {
   Plan pl{};
@@ -1062,19 +1089,20 @@ void launch_spmm_product(const Plan& pl, const int32_t* rowptr, const int32_t* c
 }
 
 template <typename T>
-void launch_update_xr(const Plan& pl, T* X, T* R, const T* P, const T* Q, const T* lam, double* part,
-                      const DevState* st, hipStream_t s) {
+void launch_update_r(const Plan& pl, T* R, const T* Q, const T* lam, double* part, const DevState* st,
+                     hipStream_t s) {
   dispatch_shape(pl, [&](auto RB, auto NAB) {
-    hipLaunchKernelGGL((k_update_xr<T, decltype(RB)::value, decltype(NAB)::value>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, X, R, P, Q, lam, part,
-                       st);
+    hipLaunchKernelGGL((k_update_r<T, decltype(RB)::value, decltype(NAB)::value>), dim3(pl.nwg), dim3(kBlock), 0, s,
+                       pl, R, Q, lam, part, st);
   });
 }
 
 template <typename T>
-void launch_update_p(const Plan& pl, T* P, const T* R, const T* beta, double* part, const DevState* st,
-                     hipStream_t s) {
+void launch_update_xp(const Plan& pl, T* X, T* P, const T* R, const T* lam, const T* beta, double* part,
+                      const DevState* st, hipStream_t s) {
   dispatch_shape(pl, [&](auto RB, auto NAB) {
-    hipLaunchKernelGGL((k_update_p<T, decltype(RB)::value, decltype(NAB)::value>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, P, R, beta, part, st);
+    hipLaunchKernelGGL((k_update_xp<T, decltype(RB)::value, decltype(NAB)::value>), dim3(pl.nwg), dim3(kBlock), 0,
+                       s, pl, X, P, R, lam, beta, part, st);
   });
 }
 
@@ -1089,8 +1117,10 @@ void launch_product(const Plan& pl, const T* X, const T* Y, double* part, const 
   }
 }
 
-void launch_reduce(const Plan& pl, const double* part, double* out, int width, const DevState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3((width + 15) / 16), dim3(kRedThreads), 0, s, part, out, width, pl.W, pl.nwg, st);
+void launch_reduce(const Plan& pl, const double* part, double* out, int width, DevState* st, hipStream_t s,
+                   int finalize) {
+  hipLaunchKernelGGL(k_reduce, dim3((width + 15) / 16), dim3(kRedThreads), 0, s, part, out, width, pl.W, pl.nwg, st,
+                     finalize);
 }
 
 void launch_solve_lambda(const Plan& pl, const double* alpha, const double* rho, double* lam, float* lam32,
@@ -1143,14 +1173,14 @@ template void launch_spmm_product<double>(const Plan&, const int32_t*, const int
                                           double*, double*, const DevState*, hipStream_t);
 template void launch_spmm_product<float>(const Plan&, const int32_t*, const int32_t*, const float*, const float*,
                                          float*, double*, const DevState*, hipStream_t);
-template void launch_update_xr<double>(const Plan&, double*, double*, const double*, const double*, const double*,
-                                       double*, const DevState*, hipStream_t);
-template void launch_update_xr<float>(const Plan&, float*, float*, const float*, const float*, const float*, double*,
-                                      const DevState*, hipStream_t);
-template void launch_update_p<double>(const Plan&, double*, const double*, const double*, double*, const DevState*,
+template void launch_update_r<double>(const Plan&, double*, const double*, const double*, double*, const DevState*,
                                       hipStream_t);
-template void launch_update_p<float>(const Plan&, float*, const float*, const float*, double*, const DevState*,
+template void launch_update_r<float>(const Plan&, float*, const float*, const float*, double*, const DevState*,
                                      hipStream_t);
+template void launch_update_xp<double>(const Plan&, double*, double*, const double*, const double*, const double*,
+                                       double*, const DevState*, hipStream_t);
+template void launch_update_xp<float>(const Plan&, float*, float*, const float*, const float*, const float*, double*,
+                                      const DevState*, hipStream_t);
 template void launch_product<double>(const Plan&, const double*, const double*, double*, const DevState*,
                                      hipStream_t);
 template void launch_product<float>(const Plan&, const float*, const float*, double*, const DevState*, hipStream_t);

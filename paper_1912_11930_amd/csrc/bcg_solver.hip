@@ -92,6 +92,7 @@ struct bcg_handle {
   double *lam = nullptr, *beta = nullptr, *ws = nullptr;
   float *lam32 = nullptr, *beta32 = nullptr;
   double *r0 = nullptr, *ratios = nullptr, *scale = nullptr;
+  int32_t* sched = nullptr;  // optional row order of the sparse product
   DevState* st = nullptr;
   DevState* st_host = nullptr;  // pinned, 2 slots
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -122,7 +123,7 @@ namespace {
 void free_all(bcg_handle* h) {
   void* ptrs[] = {h->rowptr, h->colind, h->vals, h->vals32, h->R, h->P, h->Q, h->partA, h->partR, h->partN,
                   h->alpha, h->rho, h->rnew, h->lam, h->beta, h->ws, h->lam32, h->beta32, h->r0, h->ratios,
-                  h->scale, h->st, h->R32, h->P32, h->Q32, h->D32};
+                  h->scale, h->st, h->R32, h->P32, h->Q32, h->D32, h->sched};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->st_host) (void)hipHostFree(h->st_host);
@@ -227,28 +228,28 @@ void enqueue_iteration(bcg_handle* h, const IterBuffers<T>& b, double tol, int i
   timed(h, BCG_K_SMALL, it, [&] {  // line 7
     launch_solve_lambda(pl, h->alpha, h->rho, h->lam, h->lam32, h->ws, h->st, s);
   });
-  timed(h, BCG_K_UPDATE_XR, it, [&] {  // lines 8-9 and the product of line 11
+  timed(h, BCG_K_UPDATE_R, it, [&] {  // line 9 and the product of line 11
     if (fast)
-      launch_update_xr_fast<T>(pl, b.X, b.R, b.P, b.Q, b.lam, h->partN, h->st, s);
+      launch_update_r_fast<T>(pl, b.R, b.Q, b.lam, h->partN, h->st, s);
     else
-      launch_update_xr<T>(pl, b.X, b.R, b.P, b.Q, b.lam, h->partN, h->st, s);
+      launch_update_r<T>(pl, b.R, b.Q, b.lam, h->partN, h->st, s);
   });
   if (!fast && !pl.fused) timed(h, BCG_K_PRODUCT, it, [&] { launch_product<T>(pl, b.R, b.R, h->partN, h->st, s); });
   timed(h, BCG_K_REDUCE, it, [&] { launch_reduce(pl, h->partN, h->rnew, pl.W, h->st, s); });
   timed(h, BCG_K_SMALL, it, [&] {  // stop rule, line 12
     launch_conv_beta(pl, h->rnew, h->r0, h->rho, h->beta, h->beta32, h->ws, h->ratios, h->st, tol, it, maxit, s);
   });
-  // line 13 and the recomputed rho of line 6 for the next iteration; after
-  // the last iteration these launches return at entry
-  timed(h, BCG_K_UPDATE_P, it + 1, [&] {
+  // line 8 and line 13 with the recomputed rho of line 6 for the next
+  // iteration (on the last iteration only line 8)
+  timed(h, BCG_K_UPDATE_XP, it, [&] {
     if (fast)
-      launch_update_p_fast<T>(pl, b.P, b.R, b.beta, h->partR, h->st, s);
+      launch_update_xp_fast<T>(pl, b.X, b.P, b.R, b.lam, b.beta, h->partR, h->st, s);
     else
-      launch_update_p<T>(pl, b.P, b.R, b.beta, h->partR, h->st, s);
+      launch_update_xp<T>(pl, b.X, b.P, b.R, b.lam, b.beta, h->partR, h->st, s);
   });
   if (!fast && !pl.fused)
     timed(h, BCG_K_PRODUCT, it + 1, [&] { launch_product<T>(pl, b.P, b.R, h->partR, h->st, s); });
-  timed(h, BCG_K_REDUCE, it + 1, [&] { launch_reduce(pl, h->partR, h->rho, pl.E, h->st, s); });
+  timed(h, BCG_K_REDUCE, it + 1, [&] { launch_reduce(pl, h->partR, h->rho, pl.E, h->st, s, 1); });
 }
 
 // Iterations to enqueue next: half the predicted remaining count (from the
@@ -662,6 +663,32 @@ int bcg_set_profiling(bcg_handle* h, int enable) {
 int bcg_get_kernel_times(const bcg_handle* h, bcg_kernel_time* out, int count) {
   if (!h || !out || count < 0) return fail(BCG_EINVAL, "NULL argument");
   for (int i = 0; i < count && i < BCG_NUM_KERNEL_CLASSES; ++i) out[i] = h->prof[i];
+  return BCG_OK;
+}
+
+int bcg_set_row_schedule(bcg_handle* h, const int32_t* order) {
+  if (!h) return fail(BCG_EINVAL, "handle is NULL");
+  DeviceGuard g(h->device);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (!order) {
+    h->pl.sched = nullptr;
+    return BCG_OK;
+  }
+  int rc;
+  if (!h->sched && (rc = dalloc(&h->sched, h->n))) return rc;
+  HIP_TRY(hipMemcpyAsync(h->sched, order, sizeof(int32_t) * h->n, hipMemcpyDeviceToDevice, h->stream));
+  // range check (memory safety of the product); the flag lives in the state
+  DevState z{};
+  HIP_TRY(hipMemcpyAsync(h->st, &z, sizeof z, hipMemcpyHostToDevice, h->stream));
+  launch_check_range(h->sched, h->n, &h->st->status, h->stream);
+  HIP_TRY(hipGetLastError());
+  DevState out{};
+  if ((rc = read_state(h, &out))) return rc;
+  if (out.status != 0) {
+    h->pl.sched = nullptr;
+    return fail(BCG_EINVAL, "row schedule has entries outside [0, n)");
+  }
+  h->pl.sched = h->sched;
   return BCG_OK;
 }
 

@@ -140,6 +140,38 @@ __global__ __launch_bounds__(kThreads) void k_kappa_vjp(Grid g, const double* __
   dk[c] = acc;
 }
 
+// order[e] = row of the e-th product row: x-y tiles of T x T cells in
+// row-major tile order, each swept through all z planes, x fastest inside the
+// tile (3D); the natural order in 2D.
+__global__ __launch_bounds__(kThreads) void k_schedule(Grid g, int T, int32_t* __restrict__ order) {
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= g.n) return;
+  if (g.dim != 3) {
+    order[e] = static_cast<int32_t>(e);
+    return;
+  }
+  const int64_t N = g.N;
+  const int64_t ntx = (N + T - 1) / T;
+  // tiles are visited in order; tile (ty, tx) holds w x h cells per plane
+  int64_t rem = e, ty = 0, tx = 0;
+  for (;;) {
+    const int64_t w = min<int64_t>(T, N - tx * T), hgt = min<int64_t>(T, N - ty * T);
+    const int64_t cells = w * hgt * N;
+    if (rem < cells) {
+      const int64_t z = rem / (w * hgt);
+      const int64_t r = rem - z * (w * hgt);
+      const int64_t y = ty * T + r / w, x = tx * T + r % w;
+      order[e] = static_cast<int32_t>(x + N * y + N * N * z);
+      return;
+    }
+    rem -= cells;
+    if (++tx == ntx) {
+      tx = 0;
+      ++ty;
+    }
+  }
+}
+
 bool make_grid(int dim, int N, Grid* g) {
   if ((dim != 2 && dim != 3) || N < 1) return false;
   g->dim = dim;
@@ -168,6 +200,15 @@ extern "C" int bcg_stencil_build(int dim, int N, const double* kappa, int32_t* r
   const int64_t blocks = (g.n + kThreads - 1) / kThreads;
   hipLaunchKernelGGL(k_build, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0,
                      static_cast<hipStream_t>(hip_stream), g, kappa, rowptr, colind, values);
+  return hipGetLastError() == hipSuccess ? BCG_OK : BCG_EHIP;
+}
+
+extern "C" int bcg_stencil_schedule(int dim, int N, int tile, int32_t* order, void* hip_stream) {
+  Grid g;
+  if (!make_grid(dim, N, &g) || tile < 1 || !order) return BCG_EINVAL;
+  const int64_t blocks = (g.n + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(k_schedule, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0,
+                     static_cast<hipStream_t>(hip_stream), g, tile, order);
   return hipGetLastError() == hipSuccess ? BCG_OK : BCG_EHIP;
 }
 

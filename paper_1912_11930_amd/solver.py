@@ -106,6 +106,15 @@ class BCG:
             check(self._lib.bcg_csr_outer(self._h, Y.data_ptr(), X.data_ptr(), float(alpha), out.data_ptr()))
         return out
 
+    def set_row_schedule(self, order: torch.Tensor | None) -> None:
+        """Processing order of the sparse-product rows (a permutation), or None."""
+        if order is not None:
+            _require(order, "order", torch.int32, (self.n,))
+        with torch.cuda.device(self.device):
+            self._bind_stream()
+            check(self._lib.bcg_set_row_schedule(self._h, None if order is None else order.data_ptr()))
+        self._sched = order
+
     def set_profiling(self, on: bool = True, classes=None) -> None:
         """Record HIP events around the launches of later solves.
 
@@ -162,6 +171,15 @@ def stencil(dim: int, N: int, kappa: torch.Tensor | None = None, device="cuda"):
                                             rowptr.data_ptr(), colind.data_ptr(), values.data_ptr(),
                                             _stream_ptr(device)))
     return rowptr, colind, values
+
+
+def stencil_schedule(dim: int, N: int, tile: int = 32, device="cuda") -> torch.Tensor:
+    """Tiled row order (x-y tiles swept through z) for the 3D stencil."""
+    device = torch.device(device)
+    order = torch.empty(N ** dim, dtype=torch.int32, device=device)
+    with torch.cuda.device(device):
+        check(_capi.lib().bcg_stencil_schedule(dim, N, tile, order.data_ptr(), _stream_ptr(device)))
+    return order
 
 
 def stencil_kappa_vjp(dim: int, N: int, kappa: torch.Tensor, dvalues: torch.Tensor) -> torch.Tensor:

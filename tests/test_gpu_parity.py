@@ -261,3 +261,57 @@ def test_misaligned_x_uses_generic_path():
     s = _solver(A, k, "hybrid", 4)
     s.solve(dev(B), X=Xv, tol=0.0, maxit=6)
     assert rel(host(Xv), Xo) <= FIXED_TOL
+
+
+# ------------------------------------------------ sparse-product row order
+def _tiled_order(N, T):
+    parts = []
+    for ty in range(0, N, T):
+        for tx in range(0, N, T):
+            z, y, x = np.meshgrid(np.arange(N), np.arange(ty, min(N, ty + T)), np.arange(tx, min(N, tx + T)),
+                                  indexing="ij")
+            parts.append((x + N * y + N * N * z).ravel())
+    return np.concatenate(parts).astype(np.int32)
+
+
+@pytest.mark.parametrize("N,T", [(5, 2), (13, 4), (128, 32)])
+def test_stencil_schedule_matches_definition(N, T):
+    P = _lib()
+    got = host(P.stencil_schedule(3, N, T))
+    assert np.array_equal(got, _tiled_order(N, T))
+    assert np.array_equal(host(P.stencil_schedule(2, N, T)), np.arange(N * N))
+
+
+@pytest.mark.parametrize("k,variant,p", [(16, "block", 0), (8, "hybrid", 4), (64, "hybrid", 8), (128, "global", 1),
+                                         (12, "hybrid", 3)])
+def test_row_schedule_random_and_tiled(k, variant, p):
+    # any row order of the sparse product gives the same iterates (up to the
+    # rounding order of the partial products)
+    P = _lib()
+    N = 11 if k <= 64 else 7
+    A = stencil_csr(3, N, cell_coefficients(3, N, 0.6))
+    B = rhs(A.shape[0], k, "normal", seed=21)
+    Xo, _ = oracle_solve(A, B, variant, p, tol=0.0, maxit=7)
+    for order in (np.random.default_rng(5).permutation(A.shape[0]).astype(np.int32), _tiled_order(N, 4)):
+        s = _solver(A, k, variant, p)
+        s.set_row_schedule(dev(order))
+        Xg, ig = s.solve(dev(B), tol=0.0, maxit=7)
+        assert rel(host(Xg), Xo) <= FIXED_TOL
+        s.set_row_schedule(None)
+        Xn, _ = s.solve(dev(B), tol=0.0, maxit=7)
+        assert rel(host(Xn), Xo) <= FIXED_TOL
+
+
+def test_row_schedule_rejects_out_of_range():
+    P = _lib()
+    A = stencil_csr(2, 9)
+    s = _solver(A, 8, "block", 0)
+    bad = np.arange(A.shape[0], dtype=np.int32)
+    bad[3] = A.shape[0]
+    with pytest.raises(P.BCGError) as e:
+        s.set_row_schedule(dev(bad))
+    assert e.value.status == oracle.EINVAL
+    B = rhs(A.shape[0], 8, "uniform")
+    Xo, _ = oracle_solve(A, B, "block", 0, tol=0.0, maxit=5)
+    Xg, _ = s.solve(dev(B), tol=0.0, maxit=5)      # still the natural order
+    assert rel(host(Xg), Xo) <= FIXED_TOL
