@@ -69,7 +69,9 @@ def measured_traffic(kernel: str, workload: str, variant: str, precision: str):
     return rec.get("bytes_per_launch")
 
 
-KERNEL_NAMES = {"spmm": "k_spmm_fast", "update_r": "k_update_r_fast", "update_xp": "k_update_xp_fast"}
+# row kernels of each class (matrix-core and k-specialised variants)
+KERNEL_NAMES = {"spmm": ("k_spmm_mfma", "k_spmm_fast"), "update_r": ("k_update_r_mfma", "k_update_r_fast"),
+                "update_xp": ("k_update_xp_mfma", "k_update_xp_fast")}
 COPY_BYTES = 2 << 30
 
 
@@ -124,9 +126,9 @@ def traffic_from(directory: str, workload: str, variant: str, precision: str) ->
     write = _pmc_means(db("write"), "WRITE_SIZE")
     path = os.path.join(ROOT, "profiles", "traffic.json")
     rec = json.load(open(path)) if os.path.exists(path) else {}
-    for cls, kname in KERNEL_NAMES.items():
-        fk = [v for n, v in fetch.items() if kname in n]
-        wk = [v for n, v in write.items() if kname in n]
+    for cls, knames in KERNEL_NAMES.items():
+        fk = [v for n, v in fetch.items() if any(kn in n for kn in knames)]
+        wk = [v for n, v in write.items() if any(kn in n for kn in knames)]
         if not fk or not wk:
             continue
         rd = fk[0] * 1024 * f_fetch

@@ -26,6 +26,7 @@ COMMON = [
 SOURCES = {
     "bcg_kernels.hip": [],
     "bcg_fast.hip": [],
+    "bcg_mfma.hip": [],
     "bcg_solver.hip": [],
     # bit-exact face coefficients: every operation rounded once
     "bcg_stencil.hip": ["-ffp-contract=off"],

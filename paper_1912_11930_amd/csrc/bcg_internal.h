@@ -46,11 +46,16 @@ struct Plan {
   int64_t ntiles;
   int nwg;      // workgroups of the row kernels
   int fast;     // 1: the k-specialised row kernels apply (k in {8..128}, p <= 16)
+  int mfma;     // column-group width of the matrix-core row kernels (0: not used)
   const int32_t* sched;  // processing order of the sparse-product rows (nullptr: natural)
 };
 
 Plan make_plan(int64_t n, int64_t nnz, int k, int p, int global, int dec);
 bool fast_supported(const Plan& pl);
+// matrix-core row kernels: group width for (nnz, k, p), 0 where they do not
+// apply; workgroup count that gives every XCD a wave per column group
+int mfma_width(int64_t nnz, int k, int p);
+int mfma_grid(int64_t n, int k, int w);
 
 // ---- launchers (all enqueue on `s`; none synchronises) ----
 // R = B - A X; norms partial; if with_p: P = R and <<R,R>> partial.
@@ -96,6 +101,17 @@ void launch_update_r_fast(const Plan& pl, T* R, const T* Q, const T* lam, double
                           hipStream_t s);
 template <typename T>
 void launch_update_xp_fast(const Plan& pl, T* X, T* P, const T* R, const T* lam, const T* beta, double* part,
+                           const DevState* st, hipStream_t s);
+
+// matrix-core row kernels (k a multiple of 16; see mfma_width)
+template <typename T>
+void launch_spmm_mfma(const Plan& pl, const int32_t* rowptr, const int32_t* colind, const T* vals, const T* P,
+                      T* Q, double* part, const DevState* st, hipStream_t s);
+template <typename T>
+void launch_update_r_mfma(const Plan& pl, T* R, const T* Q, const T* lam, double* part, const DevState* st,
+                          hipStream_t s);
+template <typename T>
+void launch_update_xp_mfma(const Plan& pl, T* X, T* P, const T* R, const T* lam, const T* beta, double* part,
                            const DevState* st, hipStream_t s);
 
 }  // namespace bcg

@@ -1059,6 +1059,8 @@ Plan make_plan(int64_t n, int64_t nnz, int k, int p, int global, int dec) {
   if (nwg > kMaxWG) nwg = kMaxWG;
   pl.nwg = static_cast<int>(nwg < 1 ? 1 : nwg);
   pl.fast = fast_supported(pl);
+  pl.mfma = mfma_width(nnz, k, p);
+  if (pl.mfma) pl.nwg = mfma_grid(n, k, pl.mfma);
   return pl;
 }
 

@@ -1,0 +1,705 @@
+// Row kernels of the block CG iteration on the gfx950 matrix cores.
+//
+// For k a multiple of 16 (<= 128) every operation of an iteration on a tile
+// of 16 rows is a sum of 16x16x4 FP64 matrix products (v_mfma_f64_16x16x4f64):
+//   updates   Q lambda, P lambda, P beta: A = 16 rows x 4 columns of the block
+//             vector, B = 4 x 16 entries of the coefficient block;
+//   products  <<X, Y>>: A = 4 rows of X (as X^T), B = the same 4 rows of Y.
+// Register layout of the instruction on gfx950: A (16x4) lane l holds
+// A[l & 15][l >> 4]; B (4x16) lane l holds B[l >> 4][l & 15]; the result
+// (16x16) lane l, element r holds D[4r + (l >> 4)][l & 15]. A result tile
+// ("D layout") therefore holds, in its register r, the rows 4r..4r+3 as the
+// K = 4 operand of a row reduction: block products are formed directly from
+// the tiles the updates produce, with no data movement.
+//
+// Columns are taken in groups of width w = max(p, 16) (a whole number of
+// 16-column blocks; for p < 16 a 16-column block holds 16/p groups, and the
+// coefficient tiles are zero outside their p x p diagonal blocks, which adds
+// exact zeros). Each wave owns one column group and walks 16-row tiles (the
+// sparse product: 8-row steps); the products of its group accumulate in MFMA
+// result registers and are projected onto the packed [qo][p][p] layout once
+// per workgroup.
+//
+// FP32 block vectors (refinement inner solves) are widened to FP64 for the
+// matrix products; an update is rounded to FP32 once and then applied in
+// FP32, with the FP32-rounded coefficients.
+#include <cstdlib>
+#include <stdexcept>
+#include <type_traits>
+
+#include "../../include/bcg.h"
+#include "bcg_internal.h"
+
+namespace bcg {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bool mstopped(const DevState* st) {
+  return st != nullptr && *reinterpret_cast<const volatile int*>(&st->done) != 0;
+}
+
+template <typename T>
+struct V2m;
+template <>
+struct V2m<double> {
+  using type = double2;
+};
+template <>
+struct V2m<float> {
+  using type = float2;
+};
+
+template <int K, int PW>
+struct MGeo {
+  static_assert(PW % 16 == 0 && K % PW == 0, "group width");
+  static constexpr int NB = PW / 16;          // 16-column blocks per group
+  static constexpr int NG = K / PW;           // column groups
+  static constexpr bool BREG = NB <= 2;       // coefficient operands in registers
+  static constexpr int CST = PW + 4;          // LDS row stride of staged coefficients
+  static constexpr int HS = NG * PW * PW;     // dense group products, then K norms
+};
+
+// Work of one wave: a fixed column group and a strided range of 16-row tiles.
+// With 8 or more workgroups, each XCD (workgroup b runs on XCD b % 8) takes a
+// contiguous eighth of the tiles, so neighbouring rows share its L2. Waves of
+// an XCD are dealt to the groups round robin; the host guarantees at least NG
+// waves per XCD (mfma_grid), and waves beyond a multiple of NG stay idle.
+struct WaveWork {
+  int group;
+  int64_t first, end, stride;
+};
+
+template <int NG>
+__device__ __forceinline__ WaveWork wave_work(int64_t ntiles) {
+  const int nwg = gridDim.x, b = blockIdx.x, wave = threadIdx.x >> 6;
+  int64_t lo = 0, hi = ntiles, waves, wid;
+  if (nwg < 8) {
+    waves = (int64_t)nwg * 4;
+    wid = (int64_t)b * 4 + wave;
+  } else {
+    const int x = b & 7, nx = (nwg - x + 7) >> 3;
+    const int64_t per = (ntiles + 7) / 8;
+    lo = min((int64_t)x * per, ntiles);
+    hi = min(lo + per, ntiles);
+    waves = (int64_t)nx * 4;
+    wid = (int64_t)(b >> 3) * 4 + wave;
+  }
+  const int64_t slots = waves / NG;
+  WaveWork w;
+  w.group = static_cast<int>(wid % NG);
+  w.first = wid < slots * NG ? lo + wid / NG : hi;
+  w.end = hi;
+  w.stride = slots > 0 ? slots : 1;
+  return w;
+}
+
+// Coefficient row of the B operand at k-step kk (pairs with load_a): row
+// ab*16 + 8*(kk>>1) + 2*(lane>>4) + (kk&1) of the group.
+__device__ __forceinline__ int coeff_row(int ab, int kk, int lane) {
+  return ab * 16 + 8 * (kk >> 1) + 2 * (lane >> 4) + (kk & 1);
+}
+
+// B operand of coefficient block C (packed [qo][p][p]) for column group G,
+// column jb*16 + (lane & 15): zero outside the p x p diagonal blocks.
+template <typename CT, int PW>
+__device__ __forceinline__ double coeff_b(const CT* __restrict__ C, const Plan& pl, int G, int ab, int jb, int kk,
+                                          int lane) {
+  const int row = G * PW + coeff_row(ab, kk, lane);
+  const int col = G * PW + jb * 16 + (lane & 15);
+  const int p = pl.p;
+  const int ga = row / p, gb = col / p;
+  if (ga != gb) return 0.0;
+  const int g = pl.global ? 0 : ga;
+  return static_cast<double>(C[(int64_t)g * p * p + (row - ga * p) * p + (col - gb * p)]);
+}
+
+// Coefficient operands of one wave: registers (w <= 32) or LDS (w = 64 = p,
+// one column group per workgroup).
+template <typename T, int K, int PW, int NC>
+struct Coeff {
+  using Gm = MGeo<K, PW>;
+  static constexpr int NB = Gm::NB;
+  double r[NC][Gm::BREG ? NB * NB * 4 : 1];
+  const double* lds;
+
+  // Called by every thread of the workgroup.
+  __device__ __forceinline__ void load(const T* const (&C)[NC], const bool (&use)[NC], const Plan& pl, int G,
+                                       double* smem) {
+    const int lane = threadIdx.x & 63;
+    if constexpr (Gm::BREG) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int ab = 0; ab < NB; ++ab)
+#pragma unroll
+          for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+              r[c][(ab * NB + jb) * 4 + kk] = use[c] ? coeff_b<T, PW>(C[c], pl, G, ab, jb, kk, lane) : 0.0;
+    } else {
+      static_assert(Gm::NG == 1, "LDS-staged coefficients need one group per workgroup");
+      for (int c = 0; c < NC; ++c) {
+        const T* src = C[c] + (pl.global ? 0 : (int64_t)G * PW * PW);
+        for (int e = threadIdx.x; e < PW * PW; e += kBlock) {
+          const int a = e / PW, b = e - a * PW;
+          smem[c * PW * Gm::CST + a * Gm::CST + b] = use[c] ? static_cast<double>(src[e]) : 0.0;
+        }
+      }
+      lds = smem;
+      __syncthreads();
+    }
+  }
+  __device__ __forceinline__ double b(int c, int ab, int jb, int kk, int lane) const {
+    if constexpr (Gm::BREG) {
+      return r[c][(ab * NB + jb) * 4 + kk];
+    } else {
+      return lds[c * PW * Gm::CST + coeff_row(ab, kk, lane) * Gm::CST + jb * 16 + (lane & 15)];
+    }
+  }
+};
+
+// A operand of block ab: lane l holds row (l & 15) of the tile at columns
+// ab*16 + 8h + 2*(l>>4) + e as k-step kk = 2h + e (two 16-byte loads in FP64).
+// Rows past n read row n-1 and are zeroed.
+template <typename T, int K, int PW>
+__device__ __forceinline__ void load_a(double (&a)[4], const T* __restrict__ X, int64_t row0, int64_t n, int G, int ab,
+                                       int lane) {
+  using T2 = typename V2m<T>::type;
+  const int64_t r = row0 + (lane & 15);
+  const bool ok = r < n;
+  const int64_t rc = ok ? r : n - 1;
+  const T* base = X + rc * K + G * PW + ab * 16 + 2 * (lane >> 4);
+  const T2 v0 = *reinterpret_cast<const T2*>(base);
+  const T2 v1 = *reinterpret_cast<const T2*>(base + 8);
+  a[0] = ok ? static_cast<double>(v0.x) : 0.0;
+  a[1] = ok ? static_cast<double>(v0.y) : 0.0;
+  a[2] = ok ? static_cast<double>(v1.x) : 0.0;
+  a[3] = ok ? static_cast<double>(v1.y) : 0.0;
+}
+
+// D layout element of block jb in row `row`: column G*w + jb*16 + (l & 15).
+template <int K, int PW>
+__device__ __forceinline__ int64_t d_off(int64_t row, int G, int jb, int lane) {
+  return row * K + G * PW + jb * 16 + (lane & 15);
+}
+
+// Per-wave partial products (D layout tiles per block pair) and column norms.
+template <int NB>
+struct MAcc {
+  d4 g[NB * NB];
+  double nrm[NB];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int i = 0; i < NB * NB; ++i) g[i] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < NB; ++i) nrm[i] = 0.0;
+  }
+};
+
+// acc(ab, jb) += X_tile[ab]^T Y_tile[jb] over the 16 rows (register r = rows 4r..4r+3).
+template <int NB>
+__device__ __forceinline__ void gram_tiles(MAcc<NB>& acc, const double (&x)[NB][4], const double (&y)[NB][4]) {
+#pragma unroll
+  for (int ab = 0; ab < NB; ++ab)
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc.g[ab * NB + jb] = mfma(x[ab][r], y[jb][r], acc.g[ab * NB + jb]);
+}
+
+// Combines the wave partials of the workgroup in a fixed order and writes the
+// packed partial row [qo][p][p] (+ k column norms). H: HS + K doubles of LDS.
+// SIGMA: the tiles hold rows and columns permuted by sigma(t) = 2(t&7) + (t>>3)
+// within each 16-column block.
+template <int K, int PW, bool NORMS, bool SIGMA = false>
+__device__ void finish_mfma(MAcc<PW / 16>& acc, int G, double* H, double* prow, const Plan& pl) {
+  using Gm = MGeo<K, PW>;
+  constexpr int NB = Gm::NB, HS = Gm::HS;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (NORMS) {
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb) {
+      acc.nrm[jb] += __shfl_xor(acc.nrm[jb], 16);
+      acc.nrm[jb] += __shfl_xor(acc.nrm[jb], 32);
+    }
+  }
+  __syncthreads();  // staged coefficients may share this memory
+  for (int e = tid; e < HS + K; e += kBlock) H[e] = 0.0;
+  __syncthreads();
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+      double* HG = H + G * PW * PW;
+#pragma unroll
+      for (int ab = 0; ab < NB; ++ab)
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            int ti = 4 * r + (lane >> 4), tj = lane & 15;
+            if (SIGMA) {
+              ti = 2 * (ti & 7) + (ti >> 3);
+              tj = 2 * (tj & 7) + (tj >> 3);
+            }
+            HG[(ab * 16 + ti) * PW + jb * 16 + tj] += acc.g[ab * NB + jb][r];
+          }
+      if (NORMS && lane < 16)
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) H[HS + G * PW + jb * 16 + lane] += acc.nrm[jb];
+    }
+    __syncthreads();
+  }
+  const int p = pl.p, pp = p * p;
+  for (int e = tid; e < pl.E; e += kBlock) {
+    const int g0 = e / pp, rem = e - g0 * pp, a = rem / p, b = rem - a * p;
+    const int gfirst = pl.global ? 0 : g0, glast = pl.global ? pl.q : g0 + 1;
+    double s = 0.0;
+    for (int g = gfirst; g < glast; ++g) {
+      const int ca = g * p + a, cb = g * p + b, Gi = ca / PW;
+      s += H[Gi * PW * PW + (ca - Gi * PW) * PW + (cb - Gi * PW)];
+    }
+    prow[e] = s;
+  }
+  if (NORMS)
+    for (int c = tid; c < K; c += kBlock) prow[pl.E + c] = H[HS + c];
+}
+
+template <int K, int PW, int NC>
+constexpr int smem_doubles() {
+  using Gm = MGeo<K, PW>;
+  constexpr int h = Gm::HS + K, c = Gm::BREG ? 0 : NC * PW * Gm::CST;
+  return h > c ? h : c;
+}
+
+// ------------------------------------------------------------ R update
+// R -= Q lambda (line 9), partial <<R, R>> (line 11) and the column norms.
+template <typename T, int K, int PW>
+__global__ __launch_bounds__(kBlock) void k_update_r_mfma(Plan pl, T* __restrict__ R, const T* __restrict__ Q,
+                                                          const T* __restrict__ lam, double* __restrict__ part,
+                                                          const DevState* st) {
+  if (mstopped(st)) return;
+  using Gm = MGeo<K, PW>;
+  constexpr int NB = Gm::NB;
+  __shared__ double smem[smem_doubles<K, PW, 1>()];
+  const int lane = threadIdx.x & 63;
+  const int64_t n = pl.n;
+  const WaveWork ww = wave_work<Gm::NG>((n + 15) / 16);
+  const int G = ww.group;
+  Coeff<T, K, PW, 1> cf;
+  cf.load({lam}, {true}, pl, G, smem);
+  MAcc<NB> acc;
+  acc.zero();
+  for (int64_t t = ww.first; t < ww.end; t += ww.stride) {
+    const int64_t row0 = t * 16;
+    double qa[NB][4];
+#pragma unroll
+    for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW>(qa[ab], Q, row0, n, G, ab, lane);
+    double rn[NB][4];
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb) {
+      d4 D = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ab = 0; ab < NB; ++ab)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) D = mfma(qa[ab][kk], cf.b(0, ab, jb, kk, lane), D);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + 4 * r + (lane >> 4);
+        rn[jb][r] = 0.0;
+        if (row < n) {
+          const int64_t off = d_off<K, PW>(row, G, jb, lane);
+          const T v = R[off] - static_cast<T>(D[r]);  // R - Q lambda
+          R[off] = v;
+          rn[jb][r] = static_cast<double>(v);
+        }
+        acc.nrm[jb] = fma(rn[jb][r], rn[jb][r], acc.nrm[jb]);
+      }
+    }
+    gram_tiles<NB>(acc, rn, rn);
+  }
+  finish_mfma<K, PW, true>(acc, G, smem, part + (int64_t)blockIdx.x * pl.W, pl);
+}
+
+// ------------------------------------------------------- X and P update
+// X += P lambda (line 8); unless `last`: P = R + P beta (line 13) and the
+// partial rho = <<P_new, R>> of the next iteration's line 6.
+template <typename T, int K, int PW>
+__global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restrict__ X, T* __restrict__ Pm,
+                                                           const T* __restrict__ R, const T* __restrict__ lam,
+                                                           const T* __restrict__ beta, double* __restrict__ part,
+                                                           const DevState* st) {
+  if (mstopped(st)) return;
+  const bool last = *reinterpret_cast<const volatile int*>(&st->last) != 0;
+  using Gm = MGeo<K, PW>;
+  constexpr int NB = Gm::NB;
+  __shared__ double smem[smem_doubles<K, PW, 2>()];
+  const int lane = threadIdx.x & 63;
+  const int64_t n = pl.n;
+  const WaveWork ww = wave_work<Gm::NG>((n + 15) / 16);
+  const int G = ww.group;
+  Coeff<T, K, PW, 2> cf;
+  cf.load({lam, beta}, {true, !last}, pl, G, smem);
+  MAcc<NB> acc;
+  acc.zero();
+  for (int64_t t = ww.first; t < ww.end; t += ww.stride) {
+    const int64_t row0 = t * 16;
+    double pa[NB][4];
+#pragma unroll
+    for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW>(pa[ab], Pm, row0, n, G, ab, lane);
+    double pn[NB][4], rv[NB][4];
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb) {
+      d4 Dx = {0.0, 0.0, 0.0, 0.0}, Dp = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ab = 0; ab < NB; ++ab)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) Dx = mfma(pa[ab][kk], cf.b(0, ab, jb, kk, lane), Dx);
+      if (!last) {
+#pragma unroll
+        for (int ab = 0; ab < NB; ++ab)
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) Dp = mfma(pa[ab][kk], cf.b(1, ab, jb, kk, lane), Dp);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + 4 * r + (lane >> 4);
+        pn[jb][r] = 0.0;
+        rv[jb][r] = 0.0;
+        if (row < n) {
+          const int64_t off = d_off<K, PW>(row, G, jb, lane);
+          X[off] = X[off] + static_cast<T>(Dx[r]);  // X + P lambda
+          if (!last) {
+            const T r_ = R[off];
+            const T v = r_ + static_cast<T>(Dp[r]);  // R + P beta
+            Pm[off] = v;
+            pn[jb][r] = static_cast<double>(v);
+            rv[jb][r] = static_cast<double>(r_);
+          }
+        }
+      }
+    }
+    if (!last) gram_tiles<NB>(acc, pn, rv);  // rho = <<P_new, R>>
+  }
+  finish_mfma<K, PW, false>(acc, G, smem, part + (int64_t)blockIdx.x * pl.W, pl);
+}
+
+// ---------------------------------------------------------------- SpMM
+// Q = A P with the partial alpha = <<P, Q>>. A wave takes steps of 8 rows of
+// its column group, 8 lanes per row: lane l holds columns 2(l&7), 2(l&7)+1 of
+// each 16-column block of row (l>>3) (16-byte gathers). One exchange between
+// lanes l and l^8 (DPP row_ror:8; they hold rows 2s and 2s+1, s = l>>4) gives
+// lane l column sigma(l&15) = 2(l&7) + ((l>>3)&1) of both rows: the operands
+// of two 16x16x4 products (rows 2kc + v, kc = l>>4, v = 0, 1) whose result is
+// the 8-row block product with rows and columns permuted by sigma.
+//
+// Software pipelined so that no wait on a younger load also waits for the
+// current gathers (loads retire in issue order): per step the wave issues the
+// gathers of step s, then the index chunk of the next step (CSR range loaded
+// one step earlier), then the CSR range two steps ahead and the schedule
+// entry three steps ahead, and only then consumes the gathers. All loads are
+// unconditional (clamped rows and entries).
+__device__ __forceinline__ int dpp_ror8(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false);  // row_ror:8
+}
+__device__ __forceinline__ double dpp_ror8(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = dpp_ror8(static_cast<int>(v & 0xffffffffLL));
+  const int hi = dpp_ror8(static_cast<int>(v >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// broadcast of lane `SRC` of each aligned group of 8 lanes (ds_swizzle bit
+// mode: lane = (lane & 0x18) | SRC within 32)
+template <int SRC>
+__device__ __forceinline__ int bc8_i(int x) {
+  return __builtin_amdgcn_ds_swizzle(x, (SRC << 5) | 0x18);
+}
+template <int SRC>
+__device__ __forceinline__ double bc8(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = bc8_i<SRC>(static_cast<int>(v & 0xffffffffLL));
+  const int hi = bc8_i<SRC>(static_cast<int>(v >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+template <int SRC>
+__device__ __forceinline__ float bc8(float x) {
+  return __int_as_float(bc8_i<SRC>(__float_as_int(x)));
+}
+
+// CSR range and 8 (column, value) pairs of a lane's row
+template <typename T>
+struct Row8 {
+  int j0, j1;
+  int cols[8];
+  T vs[8];
+};
+
+// lane cg of the row loads entry j + cg; entry u is then spread from lane u
+template <typename T, int U = 0>
+__device__ __forceinline__ void spread8(Row8<T>& r, int c, T v) {
+  if constexpr (U < 8) {
+    r.cols[U] = bc8_i<U>(c);
+    r.vs[U] = bc8<U>(v);
+    spread8<T, U + 1>(r, c, v);
+  }
+}
+
+template <typename T, int K, int PW>
+__global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ colind, const T* __restrict__ vals,
+                                                      const T* __restrict__ Pm, T* __restrict__ Q,
+                                                      double* __restrict__ part, const DevState* st) {
+  if (mstopped(st)) return;
+  using Gm = MGeo<K, PW>;
+  using T2 = typename V2m<T>::type;
+  constexpr int NB = Gm::NB;
+  __shared__ double smem[smem_doubles<K, PW, 0>()];
+  const int lane = threadIdx.x & 63, rr = lane >> 3, cg = lane & 7;
+  const bool odd = (lane >> 3) & 1;
+  const int64_t n = pl.n;
+  const WaveWork ww = wave_work<Gm::NG>((n + 7) / 8);
+  const int G = ww.group;
+  const int c0 = G * PW + 2 * cg;
+  MAcc<NB> acc;
+  acc.zero();
+  const int32_t* __restrict__ sched = pl.sched;
+  auto row_of = [&](int64_t step) -> int64_t {
+    int64_t e = step * 8 + rr;
+    e = e < n ? e : n - 1;
+    return sched ? static_cast<int64_t>(sched[e]) : e;
+  };
+  auto idx_load = [&](int j0, int j1, int& c, T& v) {
+    const int jj = max(min(j0 + cg, j1 - 1), 0);
+    c = colind[jj];
+    v = vals[jj];
+  };
+  const int64_t tw = ww.stride;
+  const int64_t last = ww.end > ww.first ? ww.end - 1 : ww.first;
+  int64_t s = ww.first;
+  Row8<T> cur;
+  int64_t cur_row = 0, row1 = 0, row2 = 0;
+  int nj0 = 0, nj1 = 0;  // CSR range of step s + tw
+  if (s < ww.end) {
+    cur_row = row_of(s);
+    row1 = row_of(min(s + tw, last));
+    row2 = row_of(min(s + 2 * tw, last));
+    cur.j0 = rowptr[cur_row];
+    cur.j1 = rowptr[cur_row + 1];
+    nj0 = rowptr[row1];
+    nj1 = rowptr[row1 + 1];
+    int c;
+    T v;
+    idx_load(cur.j0, cur.j1, c, v);
+    spread8<T>(cur, c, v);
+  }
+  for (; s < ww.end; s += tw) {
+    const bool ok = s * 8 + rr < n;
+    const int64_t i = cur_row;
+    // 1. gathers of the current step (first block) and the own row of P
+    T2 xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xv[u] = *reinterpret_cast<const T2*>(Pm + (int64_t)cur.cols[u] * K + c0);
+    T2 pv[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) pv[b] = *reinterpret_cast<const T2*>(Pm + i * K + c0 + 16 * b);
+    // 2. index chunk of the next step
+    Row8<T> nxt;
+    nxt.j0 = nj0;
+    nxt.j1 = nj1;
+    int nc;
+    T nv;
+    idx_load(nj0, nj1, nc, nv);
+    // 3. CSR range two steps ahead, schedule entry three steps ahead
+    nj0 = rowptr[row2];
+    nj1 = rowptr[row2 + 1];
+    const int64_t row3 = row_of(min(s + 3 * tw, last));
+    // 4. consume the gathers, block by block
+    T q[NB][2];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if (b > 0) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          xv[u] = *reinterpret_cast<const T2*>(Pm + (int64_t)cur.cols[u] * K + c0 + 16 * b);
+      }
+      T q0 = T(0), q1 = T(0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool in = cur.j0 + u < cur.j1;
+        const T a0 = fma(cur.vs[u], xv[u].x, q0);
+        const T a1 = fma(cur.vs[u], xv[u].y, q1);
+        q0 = in ? a0 : q0;
+        q1 = in ? a1 : q1;
+      }
+      q[b][0] = q0;
+      q[b][1] = q1;
+    }
+    // rows with more than 8 entries: remaining chunks without pipelining
+    for (int jb = cur.j0 + 8; jb < cur.j1; jb += 8) {
+      Row8<T> ex;
+      int c;
+      T v;
+      idx_load(jb, cur.j1, c, v);
+      spread8<T>(ex, c, v);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          xv[u] = *reinterpret_cast<const T2*>(Pm + (int64_t)ex.cols[u] * K + c0 + 16 * b);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const bool in = jb + u < cur.j1;
+          const T a0 = fma(ex.vs[u], xv[u].x, q[b][0]);
+          const T a1 = fma(ex.vs[u], xv[u].y, q[b][1]);
+          q[b][0] = in ? a0 : q[b][0];
+          q[b][1] = in ? a1 : q[b][1];
+        }
+      }
+    }
+    // store Q; exchange P and Q values between lanes l and l^8
+    double pe[NB][2], qe[NB][2];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if (ok) *reinterpret_cast<T2*>(Q + i * K + c0 + 16 * b) = T2{q[b][0], q[b][1]};
+      const double p0 = ok ? static_cast<double>(pv[b].x) : 0.0, p1 = ok ? static_cast<double>(pv[b].y) : 0.0;
+      const double q0 = ok ? static_cast<double>(q[b][0]) : 0.0, q1 = ok ? static_cast<double>(q[b][1]) : 0.0;
+      const double pr = dpp_ror8(odd ? p0 : p1), qr = dpp_ror8(odd ? q0 : q1);
+      pe[b][0] = odd ? pr : p0;
+      pe[b][1] = odd ? p1 : pr;
+      qe[b][0] = odd ? qr : q0;
+      qe[b][1] = odd ? q1 : qr;
+    }
+    // alpha = <<P, Q>> over the 8 rows (sigma-permuted)
+#pragma unroll
+    for (int ab = 0; ab < NB; ++ab)
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) acc.g[ab * NB + jb] = mfma(pe[ab][v], qe[jb][v], acc.g[ab * NB + jb]);
+    spread8<T>(nxt, nc, nv);
+    cur = nxt;
+    cur_row = row1;
+    row1 = row2;
+    row2 = row3;
+  }
+  finish_mfma<K, PW, false, true>(acc, G, smem, part + (int64_t)blockIdx.x * pl.W, pl);
+}
+
+int env_set(const char* name) {
+  const char* v = std::getenv(name);
+  return v != nullptr && v[0] != '\0' && v[0] != '0';
+}
+
+template <typename F>
+bool dispatch_mfma(const Plan& pl, F&& f) {
+  const int w = pl.mfma;
+  if (!w) return false;
+  auto withK = [&](auto Kc) -> bool {
+    constexpr int K = decltype(Kc)::value;
+    if (w == 16) {
+      f(Kc, std::integral_constant<int, 16>());
+      return true;
+    }
+    if constexpr (K % 32 == 0)
+      if (w == 32) {
+        f(Kc, std::integral_constant<int, 32>());
+        return true;
+      }
+    if constexpr (K == 64)
+      if (w == 64) {
+        f(Kc, std::integral_constant<int, 64>());
+        return true;
+      }
+    return false;
+  };
+  switch (pl.k) {
+    case 16: return withK(std::integral_constant<int, 16>());
+    case 32: return withK(std::integral_constant<int, 32>());
+    case 48: return withK(std::integral_constant<int, 48>());
+    case 64: return withK(std::integral_constant<int, 64>());
+    case 80: return withK(std::integral_constant<int, 80>());
+    case 96: return withK(std::integral_constant<int, 96>());
+    case 112: return withK(std::integral_constant<int, 112>());
+    case 128: return withK(std::integral_constant<int, 128>());
+    default: return false;
+  }
+}
+
+// the launch must give every XCD (or the whole grid below 8 workgroups) at
+// least one wave per column group
+void check_grid(const Plan& pl) {
+  const int ng = pl.k / pl.mfma;
+  const int min_waves = pl.nwg < 8 ? pl.nwg * 4 : (pl.nwg / 8) * 4;
+  if (min_waves < ng) throw std::runtime_error("matrix-core launch: fewer waves than column groups");
+}
+
+}  // namespace
+
+int mfma_width(int64_t nnz, int k, int p) {
+  if (env_set("BCG_NO_MFMA") || env_set("BCG_GENERIC_ONLY") || nnz < 1) return 0;
+  if (k % 16 != 0 || k > 128) return 0;
+  if (p <= 16 && 16 % p == 0) return 16;
+  if (p == 32 && k % 32 == 0) return 32;
+  if (p == 64 && k == 64) return 64;
+  return 0;
+}
+
+int mfma_grid(int64_t n, int k, int w) {
+  const int64_t ng = k / w;
+  const int64_t units = ((n + 15) / 16) * ng;
+  int64_t nwg = (units + 3) / 4;
+  if (nwg > kMaxWG) nwg = kMaxWG;
+  if (nwg < 1) nwg = 1;
+  if (ng > 4) {
+    if (nwg < 2) nwg = 2;
+    if (nwg >= 8 && nwg < 16) nwg = 7;
+  }
+  return static_cast<int>(nwg);
+}
+
+template <typename T>
+void launch_spmm_mfma(const Plan& pl, const int32_t* rowptr, const int32_t* colind, const T* vals, const T* P, T* Q,
+                      double* part, const DevState* st, hipStream_t s) {
+  check_grid(pl);
+  dispatch_mfma(pl, [&](auto Kc, auto Wc) {
+    hipLaunchKernelGGL((k_spmm_mfma<T, decltype(Kc)::value, decltype(Wc)::value>), dim3(pl.nwg), dim3(kBlock), 0, s,
+                       pl, rowptr, colind, vals, P, Q, part, st);
+  });
+}
+
+template <typename T>
+void launch_update_r_mfma(const Plan& pl, T* R, const T* Q, const T* lam, double* part, const DevState* st,
+                          hipStream_t s) {
+  check_grid(pl);
+  dispatch_mfma(pl, [&](auto Kc, auto Wc) {
+    hipLaunchKernelGGL((k_update_r_mfma<T, decltype(Kc)::value, decltype(Wc)::value>), dim3(pl.nwg), dim3(kBlock), 0,
+                       s, pl, R, Q, lam, part, st);
+  });
+}
+
+template <typename T>
+void launch_update_xp_mfma(const Plan& pl, T* X, T* P, const T* R, const T* lam, const T* beta, double* part,
+                           const DevState* st, hipStream_t s) {
+  check_grid(pl);
+  dispatch_mfma(pl, [&](auto Kc, auto Wc) {
+    hipLaunchKernelGGL((k_update_xp_mfma<T, decltype(Kc)::value, decltype(Wc)::value>), dim3(pl.nwg), dim3(kBlock),
+                       0, s, pl, X, P, R, lam, beta, part, st);
+  });
+}
+
+#define BCG_MFMA_INST(T)                                                                                           \
+  template void launch_spmm_mfma<T>(const Plan&, const int32_t*, const int32_t*, const T*, const T*, T*, double*, \
+                                    const DevState*, hipStream_t);                                                 \
+  template void launch_update_r_mfma<T>(const Plan&, T*, const T*, const T*, double*, const DevState*,            \
+                                        hipStream_t);                                                              \
+  template void launch_update_xp_mfma<T>(const Plan&, T*, T*, const T*, const T*, const T*, double*,              \
+                                         const DevState*, hipStream_t);
+BCG_MFMA_INST(double)
+BCG_MFMA_INST(float)
+
+}  // namespace bcg

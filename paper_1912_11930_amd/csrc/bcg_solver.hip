@@ -67,6 +67,16 @@ int dalloc(T** p, size_t count) {
   return BCG_OK;
 }
 
+// Row kernels of a solve: matrix-core kernels where the plan allows them,
+// else the k-specialised kernels (16-byte aligned X), else the generic ones.
+enum class RowPath { generic, fast, mfma };
+
+RowPath row_path(const Plan& pl, bool x_aligned) {
+  if (pl.mfma) return RowPath::mfma;
+  if (pl.fast && x_aligned) return RowPath::fast;
+  return RowPath::generic;
+}
+
 // Buffers of one precision's iteration: block vectors and coefficients.
 template <typename T>
 struct IterBuffers {
@@ -102,7 +112,7 @@ struct bcg_handle {
   int inner_maxit = 1000, max_outer = 50;
   float *R32 = nullptr, *P32 = nullptr, *Q32 = nullptr, *D32 = nullptr;
   int chunk = 32;       // upper bound on iterations enqueued per poll
-  bool fast_now = false;  // k-specialised row kernels for the current solve
+  RowPath path = RowPath::generic;  // row kernels of the current solve
   // per-kernel-class event timing
   struct ProfRec {
     int cls, it;
@@ -216,9 +226,11 @@ template <typename T>
 void enqueue_iteration(bcg_handle* h, const IterBuffers<T>& b, double tol, int it, int maxit) {
   const Plan& pl = h->pl;
   hipStream_t s = h->stream;
-  const bool fast = h->fast_now;
+  const bool mfma = h->path == RowPath::mfma, fast = mfma || h->path == RowPath::fast;
   timed(h, BCG_K_SPMM, it, [&] {  // lines 4-5
-    if (fast)
+    if (mfma)
+      launch_spmm_mfma<T>(pl, h->rowptr, h->colind, b.vals, b.P, b.Q, h->partA, h->st, s);
+    else if (fast)
       launch_spmm_fast<T>(pl, h->rowptr, h->colind, b.vals, b.P, b.Q, h->partA, h->st, s);
     else
       launch_spmm_product<T>(pl, h->rowptr, h->colind, b.vals, b.P, b.Q, h->partA, h->st, s);
@@ -229,7 +241,9 @@ void enqueue_iteration(bcg_handle* h, const IterBuffers<T>& b, double tol, int i
     launch_solve_lambda(pl, h->alpha, h->rho, h->lam, h->lam32, h->ws, h->st, s);
   });
   timed(h, BCG_K_UPDATE_R, it, [&] {  // line 9 and the product of line 11
-    if (fast)
+    if (mfma)
+      launch_update_r_mfma<T>(pl, b.R, b.Q, b.lam, h->partN, h->st, s);
+    else if (fast)
       launch_update_r_fast<T>(pl, b.R, b.Q, b.lam, h->partN, h->st, s);
     else
       launch_update_r<T>(pl, b.R, b.Q, b.lam, h->partN, h->st, s);
@@ -242,7 +256,9 @@ void enqueue_iteration(bcg_handle* h, const IterBuffers<T>& b, double tol, int i
   // line 8 and line 13 with the recomputed rho of line 6 for the next
   // iteration (on the last iteration only line 8)
   timed(h, BCG_K_UPDATE_XP, it, [&] {
-    if (fast)
+    if (mfma)
+      launch_update_xp_mfma<T>(pl, b.X, b.P, b.R, b.lam, b.beta, h->partR, h->st, s);
+    else if (fast)
       launch_update_xp_fast<T>(pl, b.X, b.P, b.R, b.lam, b.beta, h->partR, h->st, s);
     else
       launch_update_xp<T>(pl, b.X, b.P, b.R, b.lam, b.beta, h->partR, h->st, s);
@@ -379,7 +395,7 @@ int solve_fp64(bcg_handle* h, const double* B, double* X, double tol, int maxit,
   if (all_zero) return BCG_OK;
   if (maxit == 0) return BCG_NOT_CONVERGED;
   IterBuffers<double> b{h->vals, X, h->R, h->P, h->Q, h->lam, h->beta};
-  h->fast_now = h->pl.fast && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
+  h->path = row_path(h->pl, reinterpret_cast<uintptr_t>(X) % 16 == 0);
   DevState fin{};
   if ((rc = run_iterations<double>(h, b, tol, maxit, &fin))) return rc;
   *iterations = fin.iter;
@@ -447,7 +463,7 @@ int solve_refine(bcg_handle* h, const double* B, double* X, double tol, int maxi
         return rc;
       } else {
         IterBuffers<float> b{h->vals32, h->D32, h->R32, h->P32, h->Q32, h->lam32, h->beta32};
-        h->fast_now = h->pl.fast;
+        h->path = row_path(h->pl, true);
         DevState fin{};
         if ((rc = run_iterations<float>(h, b, inner_target(h->inner_tol, tol, ratio), h->inner_maxit, &fin)))
           return rc;

@@ -223,9 +223,14 @@ FAST_CASES = [(k, v, p) for k in (8, 16, 32, 64, 128) for (v, p) in
               if p <= k] + [(8, "block", 0), (16, "block", 0), (16, "global", 1), (128, "global", 8)]
 
 
+@pytest.mark.parametrize("path", ["default", "no_mfma"])
 @pytest.mark.parametrize("k,variant,p", FAST_CASES)
-def test_fast_path_fixed_iterations(k, variant, p):
-    log(f"fast k={k} {variant} p={p}")
+def test_fast_path_fixed_iterations(monkeypatch, k, variant, p, path):
+    # default: matrix-core kernels where k is a multiple of 16; no_mfma: the
+    # k-specialised vector kernels for the same shapes
+    if path == "no_mfma":
+        monkeypatch.setenv("BCG_NO_MFMA", "1")
+    log(f"fast k={k} {variant} p={p} {path}")
     N = 41 if k <= 32 else 19                      # ragged: n not a multiple of the rows per step
     A = stencil_csr(2, N, cell_coefficients(2, N, 0.8))
     B = rhs(A.shape[0], k, "normal", seed=100 + k)
@@ -250,6 +255,40 @@ def test_generic_path_forced(monkeypatch, k, variant, p):
     assert rel(host(Xg), Xo) <= FIXED_TOL
 
 
+# ------------------------------------------------ matrix-core row kernels
+# group widths 16/32/64, column-group counts 1..8 (3, 5, 7: waves per XCD not
+# a multiple of the group count), ragged row tails, grids below 8 workgroups
+MFMA_CASES = [
+    (32, "block", 0, 2, 41), (64, "block", 0, 2, 23), (64, "hybrid", 32, 2, 23), (64, "global", 32, 2, 23),
+    (96, "hybrid", 32, 2, 19), (128, "hybrid", 32, 2, 17), (128, "global", 32, 2, 17), (64, "global", 64, 2, 19),
+    (48, "hybrid", 16, 2, 29), (48, "parallel", 1, 3, 7), (80, "hybrid", 8, 2, 21), (112, "global", 16, 2, 13),
+    (112, "hybrid", 16, 2, 3), (128, "parallel", 1, 2, 10), (128, "hybrid", 2, 3, 5), (16, "block", 0, 2, 1),
+    (16, "hybrid", 4, 2, 3), (32, "global", 2, 3, 4),
+]
+
+
+@pytest.mark.parametrize("k,variant,p,dim,N", MFMA_CASES)
+def test_mfma_path_fixed_iterations(k, variant, p, dim, N):
+    log(f"mfma k={k} {variant} p={p} dim={dim} N={N}")
+    A = stencil_csr(dim, N, cell_coefficients(dim, N, 0.8))
+    B = rhs(A.shape[0], k, "normal", seed=300 + k)
+    m = 6 if A.shape[0] > 1 else 1
+    Xo, io = oracle_solve(A, B, variant, p, tol=0.0, maxit=m)
+    s = _solver(A, k, variant, p)
+    Xg, ig = s.solve(dev(B), tol=0.0, maxit=m)
+    assert ig["iterations"] == io["iterations"]
+    assert ig["status"] == io["status"]
+    assert rel(host(Xg), Xo) <= FIXED_TOL
+
+
+@pytest.mark.parametrize("variant,p", [("block", 0), ("hybrid", 32)])
+def test_mfma_path_converged_k64(variant, p):
+    log(f"mfma converged k=64 {variant} p={p}")
+    A = stencil_csr(3, 11, cell_coefficients(3, 11, 1.0))
+    B = rhs(A.shape[0], 64, "normal", seed=9)
+    _converged_case(A, B, variant, p)
+
+
 def test_misaligned_x_uses_generic_path():
     # a solution view that is not 16-byte aligned is still solved correctly
     A = stencil_csr(2, 17)
@@ -259,6 +298,19 @@ def test_misaligned_x_uses_generic_path():
     buf = torch.zeros(A.shape[0] * k + 1, dtype=torch.float64, device="cuda")
     Xv = buf[1:].view(A.shape[0], k)
     s = _solver(A, k, "hybrid", 4)
+    s.solve(dev(B), X=Xv, tol=0.0, maxit=6)
+    assert rel(host(Xv), Xo) <= FIXED_TOL
+
+
+def test_misaligned_x_matrix_core_path():
+    # the matrix-core kernels access X element-wise: any 8-byte aligned view works
+    A = stencil_csr(2, 17)
+    k = 16
+    B = rhs(A.shape[0], k, "uniform")
+    Xo, _ = oracle_solve(A, B, "hybrid", 8, tol=0.0, maxit=6)
+    buf = torch.zeros(A.shape[0] * k + 1, dtype=torch.float64, device="cuda")
+    Xv = buf[1:].view(A.shape[0], k)
+    s = _solver(A, k, "hybrid", 8)
     s.solve(dev(B), X=Xv, tol=0.0, maxit=6)
     assert rel(host(Xv), Xo) <= FIXED_TOL
 
