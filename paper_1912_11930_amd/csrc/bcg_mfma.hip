@@ -99,19 +99,28 @@ __device__ __forceinline__ WaveWork wave_work(int64_t ntiles) {
   return w;
 }
 
-// Coefficient row of the B operand at k-step kk (pairs with load_a): row
-// ab*16 + 8*(kk>>1) + 2*(lane>>4) + (kk&1) of the group.
+// Column order inside a 16-column block: position t holds column sigma(t) =
+// 2(t&7) + (t>>3), so that lanes l and l^8 hold adjacent columns.
+__device__ __forceinline__ int sigma16(int t) { return 2 * (t & 7) + (t >> 3); }
+
+// Coefficient row of the B operand at k-step kk (pairs with load_a): FP64
+// block vectors ab*16 + 8*(kk>>1) + 2*(lane>>4) + (kk&1), FP32 ab*16 +
+// 4*(lane>>4) + kk (one 16-byte load per lane and block).
+template <typename T>
 __device__ __forceinline__ int coeff_row(int ab, int kk, int lane) {
-  return ab * 16 + 8 * (kk >> 1) + 2 * (lane >> 4) + (kk & 1);
+  if constexpr (sizeof(T) == 8)
+    return ab * 16 + 8 * (kk >> 1) + 2 * (lane >> 4) + (kk & 1);
+  else
+    return ab * 16 + 4 * (lane >> 4) + kk;
 }
 
 // B operand of coefficient block C (packed [qo][p][p]) for column group G,
-// column jb*16 + (lane & 15): zero outside the p x p diagonal blocks.
+// column jb*16 + sigma(lane & 15): zero outside the p x p diagonal blocks.
 template <typename CT, int PW>
 __device__ __forceinline__ double coeff_b(const CT* __restrict__ C, const Plan& pl, int G, int ab, int jb, int kk,
                                           int lane) {
-  const int row = G * PW + coeff_row(ab, kk, lane);
-  const int col = G * PW + jb * 16 + (lane & 15);
+  const int row = G * PW + coeff_row<CT>(ab, kk, lane);
+  const int col = G * PW + jb * 16 + sigma16(lane & 15);
   const int p = pl.p;
   const int ga = row / p, gb = col / p;
   if (ga != gb) return 0.0;
@@ -159,50 +168,86 @@ struct Coeff {
     if constexpr (Gm::BREG) {
       return r[c][(ab * NB + jb) * 4 + kk];
     } else {
-      return lds[c * PW * Gm::CST + coeff_row(ab, kk, lane) * Gm::CST + jb * 16 + (lane & 15)];
+      return lds[c * PW * Gm::CST + coeff_row<T>(ab, kk, lane) * Gm::CST + jb * 16 + sigma16(lane & 15)];
     }
   }
 };
 
-// A operand of block ab: lane l holds row (l & 15) of the tile at columns
-// ab*16 + 8h + 2*(l>>4) + e as k-step kk = 2h + e (two 16-byte loads in FP64).
-// Rows past n read row n-1 and are zeroed.
+// A operand of block ab: lane l holds row (l & 15) of the tile at the
+// columns coeff_row gives for k-steps kk = 0..3 (FP64: two 16-byte loads,
+// FP32: one). Rows past n read row n-1 and are zeroed.
 template <typename T, int K, int PW>
 __device__ __forceinline__ void load_a(double (&a)[4], const T* __restrict__ X, int64_t row0, int64_t n, int G, int ab,
                                        int lane) {
-  using T2 = typename V2m<T>::type;
   const int64_t r = row0 + (lane & 15);
   const bool ok = r < n;
   const int64_t rc = ok ? r : n - 1;
-  const T* base = X + rc * K + G * PW + ab * 16 + 2 * (lane >> 4);
-  const T2 v0 = *reinterpret_cast<const T2*>(base);
-  const T2 v1 = *reinterpret_cast<const T2*>(base + 8);
-  a[0] = ok ? static_cast<double>(v0.x) : 0.0;
-  a[1] = ok ? static_cast<double>(v0.y) : 0.0;
-  a[2] = ok ? static_cast<double>(v1.x) : 0.0;
-  a[3] = ok ? static_cast<double>(v1.y) : 0.0;
+  if constexpr (sizeof(T) == 8) {
+    const T* base = X + rc * K + G * PW + ab * 16 + 2 * (lane >> 4);
+    const double2 v0 = *reinterpret_cast<const double2*>(base);
+    const double2 v1 = *reinterpret_cast<const double2*>(base + 8);
+    a[0] = ok ? v0.x : 0.0;
+    a[1] = ok ? v0.y : 0.0;
+    a[2] = ok ? v1.x : 0.0;
+    a[3] = ok ? v1.y : 0.0;
+  } else {
+    const float4 v = *reinterpret_cast<const float4*>(X + rc * K + G * PW + ab * 16 + 4 * (lane >> 4));
+    a[0] = ok ? static_cast<double>(v.x) : 0.0;
+    a[1] = ok ? static_cast<double>(v.y) : 0.0;
+    a[2] = ok ? static_cast<double>(v.z) : 0.0;
+    a[3] = ok ? static_cast<double>(v.w) : 0.0;
+  }
 }
 
-// D layout element of block jb in row `row`: column G*w + jb*16 + (l & 15).
-template <int K, int PW>
-__device__ __forceinline__ int64_t d_off(int64_t row, int G, int jb, int lane) {
-  return row * K + G * PW + jb * 16 + (lane & 15);
+// Value of lane l^8 (DPP row_ror:8 within each row of 16 lanes).
+__device__ __forceinline__ int xch(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float xch(float x) { return __int_as_float(xch(__float_as_int(x))); }
+__device__ __forceinline__ double xch(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = xch(static_cast<int>(v & 0xffffffffLL));
+  const int hi = xch(static_cast<int>(v >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
-// Per-wave partial products (D layout tiles per block pair) and column norms.
+// Pair layout of a 16 x 16 tile: lane l (s = l>>4, c = l&7, odd = bit 3)
+// holds columns 2c, 2c+1 of rows 4(2 odd + m) + s, m = 0, 1 (one 2-element
+// access per row). to_pairs converts a result tile with sigma-ordered columns
+// (element r: row 4r + s, column sigma(l&15) = 2c + odd) by one exchange of
+// two values between lanes l and l^8; from_pairs is its inverse and gives the
+// operand layout of the block products.
+template <typename T>
+__device__ __forceinline__ void to_pairs(const d4& D, T (&out)[2][2], bool odd) {
+  const T d0 = static_cast<T>(D[0]), d1 = static_cast<T>(D[1]);
+  const T d2 = static_cast<T>(D[2]), d3 = static_cast<T>(D[3]);
+  const T r0 = xch(odd ? d0 : d2), r1 = xch(odd ? d1 : d3);
+  out[0][0] = odd ? r0 : d0;
+  out[0][1] = odd ? d2 : r0;
+  out[1][0] = odd ? r1 : d1;
+  out[1][1] = odd ? d3 : r1;
+}
+template <typename T>
+__device__ __forceinline__ void from_pairs(const T (&in)[2][2], double (&x)[4], bool odd) {
+  const T r0 = xch(odd ? in[0][0] : in[0][1]), r1 = xch(odd ? in[1][0] : in[1][1]);
+  x[0] = static_cast<double>(odd ? r0 : in[0][0]);
+  x[1] = static_cast<double>(odd ? r1 : in[1][0]);
+  x[2] = static_cast<double>(odd ? in[0][1] : r0);
+  x[3] = static_cast<double>(odd ? in[1][1] : r1);
+}
+
+// Per-wave partial block products: result tiles per block pair.
 template <int NB>
 struct MAcc {
   d4 g[NB * NB];
-  double nrm[NB];
   __device__ __forceinline__ void zero() {
 #pragma unroll
     for (int i = 0; i < NB * NB; ++i) g[i] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int i = 0; i < NB; ++i) nrm[i] = 0.0;
   }
 };
 
-// acc(ab, jb) += X_tile[ab]^T Y_tile[jb] over the 16 rows (register r = rows 4r..4r+3).
+// acc(ab, jb) += X_tile[ab]^T Y_tile[jb] over 16 rows, operands in the
+// sigma-ordered result layout (register r: rows 4r + (l>>4)).
 template <int NB>
 __device__ __forceinline__ void gram_tiles(MAcc<NB>& acc, const double (&x)[NB][4], const double (&y)[NB][4]) {
 #pragma unroll
@@ -214,21 +259,14 @@ __device__ __forceinline__ void gram_tiles(MAcc<NB>& acc, const double (&x)[NB][
 }
 
 // Combines the wave partials of the workgroup in a fixed order and writes the
-// packed partial row [qo][p][p] (+ k column norms). H: HS + K doubles of LDS.
-// SIGMA: the tiles hold rows and columns permuted by sigma(t) = 2(t&7) + (t>>3)
-// within each 16-column block.
-template <int K, int PW, bool NORMS, bool SIGMA = false>
+// packed partial row [qo][p][p] (NORMS: + the k column norms, the diagonal of
+// the product <<R, R>>). The tiles hold rows and columns in sigma order within
+// each 16-column block. H: HS + K doubles of LDS.
+template <int K, int PW, bool NORMS>
 __device__ void finish_mfma(MAcc<PW / 16>& acc, int G, double* H, double* prow, const Plan& pl) {
   using Gm = MGeo<K, PW>;
   constexpr int NB = Gm::NB, HS = Gm::HS;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  if (NORMS) {
-#pragma unroll
-    for (int jb = 0; jb < NB; ++jb) {
-      acc.nrm[jb] += __shfl_xor(acc.nrm[jb], 16);
-      acc.nrm[jb] += __shfl_xor(acc.nrm[jb], 32);
-    }
-  }
   __syncthreads();  // staged coefficients may share this memory
   for (int e = tid; e < HS + K; e += kBlock) H[e] = 0.0;
   __syncthreads();
@@ -241,16 +279,9 @@ __device__ void finish_mfma(MAcc<PW / 16>& acc, int G, double* H, double* prow, 
         for (int jb = 0; jb < NB; ++jb)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            int ti = 4 * r + (lane >> 4), tj = lane & 15;
-            if (SIGMA) {
-              ti = 2 * (ti & 7) + (ti >> 3);
-              tj = 2 * (tj & 7) + (tj >> 3);
-            }
+            const int ti = sigma16(4 * r + (lane >> 4)), tj = sigma16(lane & 15);
             HG[(ab * 16 + ti) * PW + jb * 16 + tj] += acc.g[ab * NB + jb][r];
           }
-      if (NORMS && lane < 16)
-#pragma unroll
-        for (int jb = 0; jb < NB; ++jb) H[HS + G * PW + jb * 16 + lane] += acc.nrm[jb];
     }
     __syncthreads();
   }
@@ -266,7 +297,10 @@ __device__ void finish_mfma(MAcc<PW / 16>& acc, int G, double* H, double* prow, 
     prow[e] = s;
   }
   if (NORMS)
-    for (int c = tid; c < K; c += kBlock) prow[pl.E + c] = H[HS + c];
+    for (int c = tid; c < K; c += kBlock) {
+      const int Gi = c / PW, cl = c - Gi * PW;
+      prow[pl.E + c] = H[Gi * PW * PW + cl * PW + cl];
+    }
 }
 
 template <int K, int PW, int NC>
@@ -277,16 +311,19 @@ constexpr int smem_doubles() {
 }
 
 // ------------------------------------------------------------ R update
-// R -= Q lambda (line 9), partial <<R, R>> (line 11) and the column norms.
+// R -= Q lambda (line 9) and the partial <<R, R>> (line 11), whose diagonal
+// gives the column norms of the stop rule.
 template <typename T, int K, int PW>
 __global__ __launch_bounds__(kBlock) void k_update_r_mfma(Plan pl, T* __restrict__ R, const T* __restrict__ Q,
                                                           const T* __restrict__ lam, double* __restrict__ part,
                                                           const DevState* st) {
   if (mstopped(st)) return;
   using Gm = MGeo<K, PW>;
+  using T2 = typename V2m<T>::type;
   constexpr int NB = Gm::NB;
   __shared__ double smem[smem_doubles<K, PW, 1>()];
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, s16 = lane >> 4, c2 = 2 * (lane & 7);
+  const bool odd = (lane >> 3) & 1;
   const int64_t n = pl.n;
   const WaveWork ww = wave_work<Gm::NG>((n + 15) / 16);
   const int G = ww.group;
@@ -307,18 +344,23 @@ __global__ __launch_bounds__(kBlock) void k_update_r_mfma(Plan pl, T* __restrict
       for (int ab = 0; ab < NB; ++ab)
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) D = mfma(qa[ab][kk], cf.b(0, ab, jb, kk, lane), D);
+      T dq[2][2], rv[2][2];
+      to_pairs<T>(D, dq, odd);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = row0 + 4 * r + (lane >> 4);
-        rn[jb][r] = 0.0;
+      for (int m = 0; m < 2; ++m) {
+        const int64_t row = row0 + 4 * (2 * odd + m) + s16;
+        rv[m][0] = rv[m][1] = T(0);
         if (row < n) {
-          const int64_t off = d_off<K, PW>(row, G, jb, lane);
-          const T v = R[off] - static_cast<T>(D[r]);  // R - Q lambda
-          R[off] = v;
-          rn[jb][r] = static_cast<double>(v);
+          T2* ptr = reinterpret_cast<T2*>(R + row * K + G * PW + jb * 16 + c2);
+          T2 r = *ptr;
+          r.x = r.x - dq[m][0];  // R - Q lambda
+          r.y = r.y - dq[m][1];
+          *ptr = r;
+          rv[m][0] = r.x;
+          rv[m][1] = r.y;
         }
-        acc.nrm[jb] = fma(rn[jb][r], rn[jb][r], acc.nrm[jb]);
       }
+      from_pairs<T>(rv, rn[jb], odd);
     }
     gram_tiles<NB>(acc, rn, rn);
   }
@@ -336,9 +378,11 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restric
   if (mstopped(st)) return;
   const bool last = *reinterpret_cast<const volatile int*>(&st->last) != 0;
   using Gm = MGeo<K, PW>;
+  using T2 = typename V2m<T>::type;
   constexpr int NB = Gm::NB;
   __shared__ double smem[smem_doubles<K, PW, 2>()];
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, s16 = lane >> 4, c2 = 2 * (lane & 7);
+  const bool odd = (lane >> 3) & 1;
   const int64_t n = pl.n;
   const WaveWork ww = wave_work<Gm::NG>((n + 15) / 16);
   const int G = ww.group;
@@ -351,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restric
     double pa[NB][4];
 #pragma unroll
     for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW>(pa[ab], Pm, row0, n, G, ab, lane);
-    double pn[NB][4], rv[NB][4];
+    double pn[NB][4], rd[NB][4];
 #pragma unroll
     for (int jb = 0; jb < NB; ++jb) {
       d4 Dx = {0.0, 0.0, 0.0, 0.0}, Dp = {0.0, 0.0, 0.0, 0.0};
@@ -359,31 +403,45 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restric
       for (int ab = 0; ab < NB; ++ab)
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) Dx = mfma(pa[ab][kk], cf.b(0, ab, jb, kk, lane), Dx);
+      T dx[2][2], dp[2][2], pv[2][2], rv[2][2];
+      to_pairs<T>(Dx, dx, odd);
       if (!last) {
 #pragma unroll
         for (int ab = 0; ab < NB; ++ab)
 #pragma unroll
           for (int kk = 0; kk < 4; ++kk) Dp = mfma(pa[ab][kk], cf.b(1, ab, jb, kk, lane), Dp);
+        to_pairs<T>(Dp, dp, odd);
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = row0 + 4 * r + (lane >> 4);
-        pn[jb][r] = 0.0;
-        rv[jb][r] = 0.0;
+      for (int m = 0; m < 2; ++m) {
+        const int64_t row = row0 + 4 * (2 * odd + m) + s16;
+        pv[m][0] = pv[m][1] = rv[m][0] = rv[m][1] = T(0);
         if (row < n) {
-          const int64_t off = d_off<K, PW>(row, G, jb, lane);
-          X[off] = X[off] + static_cast<T>(Dx[r]);  // X + P lambda
+          const int64_t off = row * K + G * PW + jb * 16 + c2;
+          T2* xp = reinterpret_cast<T2*>(X + off);
+          T2 x = *xp;
+          x.x = x.x + dx[m][0];  // X + P lambda
+          x.y = x.y + dx[m][1];
+          *xp = x;
           if (!last) {
-            const T r_ = R[off];
-            const T v = r_ + static_cast<T>(Dp[r]);  // R + P beta
-            Pm[off] = v;
-            pn[jb][r] = static_cast<double>(v);
-            rv[jb][r] = static_cast<double>(r_);
+            const T2 r = *reinterpret_cast<const T2*>(R + off);
+            T2 pnew;
+            pnew.x = r.x + dp[m][0];  // R + P beta
+            pnew.y = r.y + dp[m][1];
+            *reinterpret_cast<T2*>(Pm + off) = pnew;
+            pv[m][0] = pnew.x;
+            pv[m][1] = pnew.y;
+            rv[m][0] = r.x;
+            rv[m][1] = r.y;
           }
         }
       }
+      if (!last) {
+        from_pairs<T>(pv, pn[jb], odd);
+        from_pairs<T>(rv, rd[jb], odd);
+      }
     }
-    if (!last) gram_tiles<NB>(acc, pn, rv);  // rho = <<P_new, R>>
+    if (!last) gram_tiles<NB>(acc, pn, rd);  // rho = <<P_new, R>>
   }
   finish_mfma<K, PW, false>(acc, G, smem, part + (int64_t)blockIdx.x * pl.W, pl);
 }
@@ -587,7 +645,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __
     row1 = row2;
     row2 = row3;
   }
-  finish_mfma<K, PW, false, true>(acc, G, smem, part + (int64_t)blockIdx.x * pl.W, pl);
+  finish_mfma<K, PW, false>(acc, G, smem, part + (int64_t)blockIdx.x * pl.W, pl);
 }
 
 int env_set(const char* name) {

@@ -68,12 +68,14 @@ int dalloc(T** p, size_t count) {
 }
 
 // Row kernels of a solve: matrix-core kernels where the plan allows them,
-// else the k-specialised kernels (16-byte aligned X), else the generic ones.
+// else the k-specialised kernels, else the generic ones. The first two access
+// X two elements at a time and need it 16-byte aligned.
 enum class RowPath { generic, fast, mfma };
 
 RowPath row_path(const Plan& pl, bool x_aligned) {
+  if (!x_aligned) return RowPath::generic;
   if (pl.mfma) return RowPath::mfma;
-  if (pl.fast && x_aligned) return RowPath::fast;
+  if (pl.fast) return RowPath::fast;
   return RowPath::generic;
 }
 

@@ -302,8 +302,8 @@ def test_misaligned_x_uses_generic_path():
     assert rel(host(Xv), Xo) <= FIXED_TOL
 
 
-def test_misaligned_x_matrix_core_path():
-    # the matrix-core kernels access X element-wise: any 8-byte aligned view works
+def test_misaligned_x_k16():
+    # k a multiple of 16 (matrix-core shapes) with an X view that is only 8-byte aligned
     A = stencil_csr(2, 17)
     k = 16
     B = rhs(A.shape[0], k, "uniform")
