@@ -102,6 +102,9 @@ __device__ __forceinline__ WaveWork wave_work(int64_t ntiles) {
 // Column order inside a 16-column block: position t holds column sigma(t) =
 // 2(t&7) + (t>>3), so that lanes l and l^8 hold adjacent columns.
 __device__ __forceinline__ int sigma16(int t) { return 2 * (t & 7) + (t >> 3); }
+// Column order of the FP32 sparse product's operands: tau(t) = 4(t&3) + (t>>2).
+__device__ __forceinline__ int tau16(int t) { return 4 * (t & 3) + (t >> 2); }
+enum class Perm { sigma, tau };
 
 // Coefficient row of the B operand at k-step kk (pairs with load_a): FP64
 // block vectors ab*16 + 8*(kk>>1) + 2*(lane>>4) + (kk&1), FP32 ab*16 +
@@ -261,8 +264,9 @@ __device__ __forceinline__ void gram_tiles(MAcc<NB>& acc, const double (&x)[NB][
 // Combines the wave partials of the workgroup in a fixed order and writes the
 // packed partial row [qo][p][p] (NORMS: + the k column norms, the diagonal of
 // the product <<R, R>>). The tiles hold rows and columns in sigma order within
-// each 16-column block. H: HS + K doubles of LDS.
-template <int K, int PW, bool NORMS>
+// each 16-column block (tau order for the FP32 sparse product). H: HS + K
+// doubles of LDS.
+template <int K, int PW, bool NORMS, Perm PM = Perm::sigma>
 __device__ void finish_mfma(MAcc<PW / 16>& acc, int G, double* H, double* prow, const Plan& pl) {
   using Gm = MGeo<K, PW>;
   constexpr int NB = Gm::NB, HS = Gm::HS;
@@ -279,7 +283,8 @@ __device__ void finish_mfma(MAcc<PW / 16>& acc, int G, double* H, double* prow, 
         for (int jb = 0; jb < NB; ++jb)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int ti = sigma16(4 * r + (lane >> 4)), tj = sigma16(lane & 15);
+            const int ti = PM == Perm::sigma ? sigma16(4 * r + (lane >> 4)) : tau16(4 * r + (lane >> 4));
+            const int tj = PM == Perm::sigma ? sigma16(lane & 15) : tau16(lane & 15);
             HG[(ab * 16 + ti) * PW + jb * 16 + tj] += acc.g[ab * NB + jb][r];
           }
     }
@@ -648,6 +653,191 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __
   finish_mfma<K, PW, false>(acc, G, smem, part + (int64_t)blockIdx.x * pl.W, pl);
 }
 
+// FP32 variant: 4 lanes per row and 16 rows per step, lane l holding columns
+// 4(l&3)..4(l&3)+3 of each block of row (l>>2) (16-byte gathers). The (column,
+// value) pairs of a row are loaded two per lane and broadcast within the quad
+// (DPP quad_perm). A 4 x 4 transpose among lanes l, l^4, l^8, l^12 (three XOR
+// swizzles) gives lane l column tau(l&15) = 4(l&3) + ((l>>2)&3) of rows
+// 4s + m (s = l>>4, m = 0..3): the operands of four 16x16x4 products.
+template <int I>
+__device__ __forceinline__ int quad_bcast(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, I * 0x55, 0xF, 0xF, false);  // quad_perm [I,I,I,I]
+}
+template <int I>
+__device__ __forceinline__ float quad_bcast(float x) {
+  return __int_as_float(quad_bcast<I>(__float_as_int(x)));
+}
+template <int D>
+__device__ __forceinline__ float xor4(float x) {
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), ((4 * D) << 10) | 0x1F));
+}
+__device__ __forceinline__ float pick4(const float (&v)[4], int i) {
+  return i == 0 ? v[0] : i == 1 ? v[1] : i == 2 ? v[2] : v[3];
+}
+// in v[e] = X[row t][e], out w[m] = X[row m][t] within the 4 lanes (t = (l>>2)&3)
+__device__ __forceinline__ void transpose4(const float (&v)[4], double (&w)[4], int t) {
+  const float s1 = xor4<1>(pick4(v, t ^ 1)), s2 = xor4<2>(pick4(v, t ^ 2)), s3 = xor4<3>(pick4(v, t ^ 3));
+  const float own = pick4(v, t);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int d = m ^ t;
+    w[m] = static_cast<double>(d == 0 ? own : d == 1 ? s1 : d == 2 ? s2 : s3);
+  }
+}
+
+struct Row8f {
+  int j0, j1;
+  int cols[8];
+  float vs[8];
+};
+
+template <int U = 0>
+__device__ __forceinline__ void spread_quad(Row8f& r, const int (&c)[2], const float (&v)[2]) {
+  if constexpr (U < 8) {
+    r.cols[U] = quad_bcast<U & 3>(c[U >> 2]);
+    r.vs[U] = quad_bcast<U & 3>(v[U >> 2]);
+    spread_quad<U + 1>(r, c, v);
+  }
+}
+
+template <int K, int PW>
+__global__ __launch_bounds__(kBlock) void k_spmm_mfma_f32(Plan pl, const int32_t* __restrict__ rowptr,
+                                                          const int32_t* __restrict__ colind,
+                                                          const float* __restrict__ vals, const float* __restrict__ Pm,
+                                                          float* __restrict__ Q, double* __restrict__ part,
+                                                          const DevState* st) {
+  if (mstopped(st)) return;
+  using Gm = MGeo<K, PW>;
+  constexpr int NB = Gm::NB;
+  __shared__ double smem[smem_doubles<K, PW, 0>()];
+  const int lane = threadIdx.x & 63, rr = lane >> 2, cq = lane & 3, tq = (lane >> 2) & 3;
+  const int64_t n = pl.n;
+  const WaveWork ww = wave_work<Gm::NG>((n + 15) / 16);
+  const int G = ww.group;
+  const int c0 = G * PW + 4 * cq;
+  MAcc<NB> acc;
+  acc.zero();
+  const int32_t* __restrict__ sched = pl.sched;
+  auto row_of = [&](int64_t step) -> int64_t {
+    int64_t e = step * 16 + rr;
+    e = e < n ? e : n - 1;
+    return sched ? static_cast<int64_t>(sched[e]) : e;
+  };
+  auto idx_load = [&](int j0, int j1, int (&c)[2], float (&v)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int jj = max(min(j0 + cq + 4 * h, j1 - 1), 0);
+      c[h] = colind[jj];
+      v[h] = vals[jj];
+    }
+  };
+  const int64_t tw = ww.stride;
+  const int64_t last = ww.end > ww.first ? ww.end - 1 : ww.first;
+  int64_t s = ww.first;
+  Row8f cur;
+  int64_t cur_row = 0, row1 = 0, row2 = 0;
+  int nj0 = 0, nj1 = 0;
+  if (s < ww.end) {
+    cur_row = row_of(s);
+    row1 = row_of(min(s + tw, last));
+    row2 = row_of(min(s + 2 * tw, last));
+    cur.j0 = rowptr[cur_row];
+    cur.j1 = rowptr[cur_row + 1];
+    nj0 = rowptr[row1];
+    nj1 = rowptr[row1 + 1];
+    int c[2];
+    float v[2];
+    idx_load(cur.j0, cur.j1, c, v);
+    spread_quad(cur, c, v);
+  }
+  for (; s < ww.end; s += tw) {
+    const bool ok = s * 16 + rr < n;
+    const int64_t i = cur_row;
+    float4 xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xv[u] = *reinterpret_cast<const float4*>(Pm + (int64_t)cur.cols[u] * K + c0);
+    float4 pv[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) pv[b] = *reinterpret_cast<const float4*>(Pm + i * K + c0 + 16 * b);
+    Row8f nxt;
+    nxt.j0 = nj0;
+    nxt.j1 = nj1;
+    int nc[2];
+    float nv[2];
+    idx_load(nj0, nj1, nc, nv);
+    nj0 = rowptr[row2];
+    nj1 = rowptr[row2 + 1];
+    const int64_t row3 = row_of(min(s + 3 * tw, last));
+    float q[NB][4];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if (b > 0) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          xv[u] = *reinterpret_cast<const float4*>(Pm + (int64_t)cur.cols[u] * K + c0 + 16 * b);
+      }
+      float a[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool in = cur.j0 + u < cur.j1;
+        const float x[4] = {xv[u].x, xv[u].y, xv[u].z, xv[u].w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float t = fmaf(cur.vs[u], x[e], a[e]);
+          a[e] = in ? t : a[e];
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) q[b][e] = a[e];
+    }
+    for (int jb = cur.j0 + 8; jb < cur.j1; jb += 8) {
+      Row8f ex;
+      int c[2];
+      float v[2];
+      idx_load(jb, cur.j1, c, v);
+      spread_quad(ex, c, v);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          xv[u] = *reinterpret_cast<const float4*>(Pm + (int64_t)ex.cols[u] * K + c0 + 16 * b);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const bool in = jb + u < cur.j1;
+          const float x[4] = {xv[u].x, xv[u].y, xv[u].z, xv[u].w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float t = fmaf(ex.vs[u], x[e], q[b][e]);
+            q[b][e] = in ? t : q[b][e];
+          }
+        }
+      }
+    }
+    double pt[NB][4], qt[NB][4];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if (ok) *reinterpret_cast<float4*>(Q + i * K + c0 + 16 * b) = float4{q[b][0], q[b][1], q[b][2], q[b][3]};
+      const float pz[4] = {ok ? pv[b].x : 0.f, ok ? pv[b].y : 0.f, ok ? pv[b].z : 0.f, ok ? pv[b].w : 0.f};
+      const float qz[4] = {ok ? q[b][0] : 0.f, ok ? q[b][1] : 0.f, ok ? q[b][2] : 0.f, ok ? q[b][3] : 0.f};
+      transpose4(pz, pt[b], tq);
+      transpose4(qz, qt[b], tq);
+    }
+    // alpha = <<P, Q>> over the 16 rows (tau-ordered)
+#pragma unroll
+    for (int ab = 0; ab < NB; ++ab)
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc.g[ab * NB + jb] = mfma(pt[ab][m], qt[jb][m], acc.g[ab * NB + jb]);
+    spread_quad(nxt, nc, nv);
+    cur = nxt;
+    cur_row = row1;
+    row1 = row2;
+    row2 = row3;
+  }
+  finish_mfma<K, PW, false, Perm::tau>(acc, G, smem, part + (int64_t)blockIdx.x * pl.W, pl);
+}
+
 int env_set(const char* name) {
   const char* v = std::getenv(name);
   return v != nullptr && v[0] != '\0' && v[0] != '0';
@@ -725,8 +915,12 @@ void launch_spmm_mfma(const Plan& pl, const int32_t* rowptr, const int32_t* coli
                       double* part, const DevState* st, hipStream_t s) {
   check_grid(pl);
   dispatch_mfma(pl, [&](auto Kc, auto Wc) {
-    hipLaunchKernelGGL((k_spmm_mfma<T, decltype(Kc)::value, decltype(Wc)::value>), dim3(pl.nwg), dim3(kBlock), 0, s,
-                       pl, rowptr, colind, vals, P, Q, part, st);
+    if constexpr (std::is_same<T, float>::value)
+      hipLaunchKernelGGL((k_spmm_mfma_f32<decltype(Kc)::value, decltype(Wc)::value>), dim3(pl.nwg), dim3(kBlock), 0,
+                         s, pl, rowptr, colind, vals, P, Q, part, st);
+    else
+      hipLaunchKernelGGL((k_spmm_mfma<T, decltype(Kc)::value, decltype(Wc)::value>), dim3(pl.nwg), dim3(kBlock), 0,
+                         s, pl, rowptr, colind, vals, P, Q, part, st);
   });
 }
 

@@ -44,6 +44,7 @@ def test_refine_reaches_fp64_accuracy(variant, p):
     Xh = host(X)
     assert info["status"] == oracle.OK, info
     assert info["outer_iterations"] >= 2
+    assert info["fp64_fallback"] == 0
     assert _true_ratio(A, B, Xh) <= tol
     Xref = np.column_stack([spla.spsolve(A.tocsc(), B[:, j]) for j in range(B.shape[1])])
     assert rel(Xh, Xref) <= 1e-7
@@ -51,6 +52,36 @@ def test_refine_reaches_fp64_accuracy(variant, p):
     s64 = P.BCG(*csr_to_dev(A), k=16, subalgebra=variant, p=p)
     X64, i64 = s64.solve(dev(B), tol=tol)
     assert rel(Xh, host(X64)) <= 1e-7
+
+
+FP32_CASES = [(16, "block", 0), (16, "hybrid", 4), (16, "parallel", 1), (32, "block", 0), (64, "hybrid", 32),
+              (48, "hybrid", 16), (8, "hybrid", 4), (12, "hybrid", 3)]
+
+
+@pytest.mark.parametrize("path", ["default", "no_mfma"])
+@pytest.mark.parametrize("k,variant,p", FP32_CASES)
+def test_fp32_inner_iterations_match_oracle(monkeypatch, k, variant, p, path):
+    """One refinement step with 6 FP32 inner iterations against the oracle's.
+
+    Both sides compute the same FP32 iterates up to rounding order (products
+    accumulated in FP64 on both); after 6 iterations they agree to ~1e-6
+    relative, a wrong product or update is off by O(1). Tolerance 1e-4.
+    """
+    if path == "no_mfma":
+        monkeypatch.setenv("BCG_NO_MFMA", "1")
+    from oracle import refine
+    log(f"fp32 inner k={k} {variant} p={p} {path}")
+    P = _P()
+    A = stencil_csr(2, 27, cell_coefficients(2, 27, 0.6))
+    B = rhs(A.shape[0], k, "normal", seed=40 + k)
+    Xo, io = refine.solve(A, B, variant, p, tol=1e-14, maxit=1, inner_tol=1e-4, inner_maxit=6)
+    s = P.BCG(*csr_to_dev(A), k=k, subalgebra=variant, p=p)
+    s.set_precision("fp32_refine", inner_tol=1e-4, inner_maxit=6, max_outer=1)
+    X, info = s.solve(dev(B), tol=1e-14)
+    assert io["status"] == info["status"] == oracle.NOT_CONVERGED
+    assert not io["fp64_fallback"] and info["fp64_fallback"] == 0
+    assert io["iterations"] == info["iterations"] == 6
+    assert rel(host(X), Xo) <= 1e-4
 
 
 def test_refine_stagnation_falls_back_to_fp64():
