@@ -10,6 +10,9 @@ namespace bcg {
 constexpr int kBlock = 256;        // threads per workgroup of the row kernels
 constexpr int kTileElems = 1024;   // rows*k elements staged per LDS tile
 constexpr int kMaxWG = 1024;       // cap on workgroups of the row kernels
+constexpr int kMaxSpWG = 16384;    // cap on workgroups of the chunked sparse product
+constexpr int kRedSplits = 64;     // first-stage row splits of a reduction over many rows
+constexpr int kRedSplitRows = 2048;  // reductions over more rows take two stages
 constexpr int kNabMax = 8;         // entry blocks per thread in fused products
 constexpr int kLamLds = 2048;      // coefficient entries kept in LDS
 
@@ -47,6 +50,11 @@ struct Plan {
   int nwg;      // workgroups of the row kernels
   int fast;     // 1: the k-specialised row kernels apply (k in {8..128}, p <= 16)
   int mfma;     // column-group width of the matrix-core row kernels (0: not used)
+  // sparse product of the matrix-core path, per precision (0: FP64, 1: FP32):
+  // workgroups and steps per wave of its chunked grid (0 steps: persistent
+  // grid of nwg workgroups)
+  int sp_nwg[2];
+  int sp_chunk[2];
   const int32_t* sched;  // processing order of the sparse-product rows (nullptr: natural)
 };
 
@@ -56,6 +64,8 @@ bool fast_supported(const Plan& pl);
 // apply; workgroup count that gives every XCD a wave per column group
 int mfma_width(int64_t nnz, int k, int p);
 int mfma_grid(int64_t n, int k, int w);
+// chunked sparse-product grid of the matrix-core path (sets sp_nwg, sp_chunk)
+void mfma_sp_grid(Plan& pl);
 
 // ---- launchers (all enqueue on `s`; none synchronises) ----
 // R = B - A X; norms partial; if with_p: P = R and <<R,R>> partial.
@@ -80,8 +90,10 @@ template <typename T>
 void launch_product(const Plan& pl, const T* X, const T* Y, double* part, const DevState* st, hipStream_t s);
 // finalize: the reduction after the X/P pass; on the last iteration it sets
 // `done` instead of reducing.
+// rows: partial rows to sum (-1: nwg); more than kRedSplitRows rows are
+// summed in two stages through `scratch` (kRedSplits rows of width W).
 void launch_reduce(const Plan& pl, const double* part, double* out, int width, DevState* st, hipStream_t s,
-                   int finalize = 0);
+                   int finalize = 0, int rows = -1, double* scratch = nullptr);
 void launch_solve_lambda(const Plan& pl, const double* alpha, const double* rho, double* lam, float* lam32,
                          double* ws, DevState* st, hipStream_t s);
 void launch_conv_beta(const Plan& pl, const double* red_new, const double* r0, const double* rho_old,

@@ -475,6 +475,37 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict
   if (s == 0 && e < width) out[e] = sh[0][le];
 }
 
+// First stage for many partial rows: block (eb, q) sums its share of the rows
+// for 16 entries into row q of `out` (kRedSplits rows of stride W), in the
+// same fixed order as k_reduce; k_reduce then sums the kRedSplits rows.
+__global__ __launch_bounds__(kRedThreads) void k_reduce_rows(const double* __restrict__ part, double* __restrict__ out,
+                                                             int width, int W, int rows, const DevState* st) {
+  if (stopped(st)) return;
+  __shared__ double sh[64][16];
+  const int tid = threadIdx.x, le = tid & 15, s = tid >> 4;
+  const int e = blockIdx.x * 16 + le, q = blockIdx.y;
+  const int r0 = static_cast<int>(static_cast<int64_t>(rows) * q / kRedSplits);
+  const int r1 = static_cast<int>(static_cast<int64_t>(rows) * (q + 1) / kRedSplits);
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+  if (e < width) {
+    int w = r0 + s;
+    for (; w + 192 < r1; w += 256) {
+      c0 += part[(int64_t)w * W + e];
+      c1 += part[(int64_t)(w + 64) * W + e];
+      c2 += part[(int64_t)(w + 128) * W + e];
+      c3 += part[(int64_t)(w + 192) * W + e];
+    }
+    for (; w < r1; w += 64) c0 += part[(int64_t)w * W + e];
+  }
+  sh[s][le] = (c0 + c1) + (c2 + c3);
+  __syncthreads();
+  for (int h = 32; h > 0; h >>= 1) {
+    if (s < h) sh[s][le] = sh[s][le] + sh[s + h][le];
+    __syncthreads();
+  }
+  if (s == 0 && e < width) out[(int64_t)q * W + e] = sh[0][le];
+}
+
 constexpr int kSmallLdsP = 48;  // p x p solves of up to this size run in LDS
 
 // lambda_g = sym(alpha_g)^{-1} rho_g by Cholesky (Algorithm 1 line 7).
@@ -1060,7 +1091,10 @@ Plan make_plan(int64_t n, int64_t nnz, int k, int p, int global, int dec) {
   pl.nwg = static_cast<int>(nwg < 1 ? 1 : nwg);
   pl.fast = fast_supported(pl);
   pl.mfma = mfma_width(nnz, k, p);
-  if (pl.mfma) pl.nwg = mfma_grid(n, k, pl.mfma);
+  if (pl.mfma) {
+    pl.nwg = mfma_grid(n, k, pl.mfma);
+    mfma_sp_grid(pl);
+  }
   return pl;
 }
 
@@ -1120,8 +1154,15 @@ void launch_product(const Plan& pl, const T* X, const T* Y, double* part, const 
 }
 
 void launch_reduce(const Plan& pl, const double* part, double* out, int width, DevState* st, hipStream_t s,
-                   int finalize) {
-  hipLaunchKernelGGL(k_reduce, dim3((width + 15) / 16), dim3(kRedThreads), 0, s, part, out, width, pl.W, pl.nwg, st,
+                   int finalize, int rows, double* scratch) {
+  if (rows < 0) rows = pl.nwg;
+  if (rows > kRedSplitRows && scratch != nullptr) {
+    hipLaunchKernelGGL(k_reduce_rows, dim3((width + 15) / 16, kRedSplits), dim3(kRedThreads), 0, s, part, scratch,
+                       width, pl.W, rows, st);
+    part = scratch;
+    rows = kRedSplits;
+  }
+  hipLaunchKernelGGL(k_reduce, dim3((width + 15) / 16), dim3(kRedThreads), 0, s, part, out, width, pl.W, rows, st,
                      finalize);
 }
 

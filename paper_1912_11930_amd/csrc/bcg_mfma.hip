@@ -23,6 +23,7 @@
 // FP32 block vectors (refinement inner solves) are widened to FP64 for the
 // matrix products; an update is rounded to FP32 once and then applied in
 // FP32, with the FP32-rounded coefficients.
+#include <cmath>
 #include <cstdlib>
 #include <stdexcept>
 #include <type_traits>
@@ -105,6 +106,44 @@ __device__ __forceinline__ int sigma16(int t) { return 2 * (t & 7) + (t >> 3); }
 // Column order of the FP32 sparse product's operands: tau(t) = 4(t&3) + (t>>2).
 __device__ __forceinline__ int tau16(int t) { return 4 * (t & 3) + (t >> 2); }
 enum class Perm { sigma, tau };
+// Column order of the result tiles of the updates: sigma for FP64 block
+// vectors (pair layout), tau for FP32 (quad layout).
+template <typename T>
+__device__ __forceinline__ int ord16(int t) {
+  return sizeof(T) == 8 ? sigma16(t) : tau16(t);
+}
+template <typename T>
+constexpr Perm perm_of() {
+  return sizeof(T) == 8 ? Perm::sigma : Perm::tau;
+}
+
+// Work of one wave in the chunked grid of the sparse product: workgroup b
+// (XCD x = b % 8) takes a chunk of `chunk` steps per wave inside XCD x's
+// contiguous eighth of the steps, so that the workgroups in flight on an XCD
+// always cover a short, contiguous stretch of rows (the hardware dispatches
+// them in order). With NG | 4 the waves of a workgroup share the NG column
+// groups (4/NG waves each, interleaved over the chunk); otherwise each wave
+// takes one group of a block of four (waves past NG stay idle).
+template <int NG>
+__device__ __forceinline__ WaveWork wave_work_sp(int64_t nsteps, int chunk) {
+  if (chunk == 0) return wave_work<NG>(nsteps);
+  constexpr bool SHARE = NG <= 4 && 4 % NG == 0;
+  constexpr int NGB = SHARE ? 1 : (NG + 3) / 4, WPG = SHARE ? 4 / NG : 1;
+  const int b = blockIdx.x, wave = threadIdx.x >> 6;
+  const int x = b & 7, lb = b >> 3, gb = lb % NGB, c = lb / NGB;
+  const int64_t per = (nsteps + 7) / 8;
+  const int64_t lo = min((int64_t)x * per, nsteps), hi = min(lo + per, nsteps);
+  const int64_t span = (int64_t)chunk * WPG, c0 = lo + (int64_t)c * span;
+  const int G = SHARE ? wave % NG : gb * 4 + wave;
+  const int widx = SHARE ? wave / NG : 0;
+  const bool idle = G >= NG;
+  WaveWork w;
+  w.group = idle ? 0 : G;
+  w.first = idle ? hi : c0 + widx;
+  w.end = min(c0 + span, hi);
+  w.stride = WPG;
+  return w;
+}
 
 // Coefficient row of the B operand at k-step kk (pairs with load_a): FP64
 // block vectors ab*16 + 8*(kk>>1) + 2*(lane>>4) + (kk&1), FP32 ab*16 +
@@ -123,7 +162,7 @@ template <typename CT, int PW>
 __device__ __forceinline__ double coeff_b(const CT* __restrict__ C, const Plan& pl, int G, int ab, int jb, int kk,
                                           int lane) {
   const int row = G * PW + coeff_row<CT>(ab, kk, lane);
-  const int col = G * PW + jb * 16 + sigma16(lane & 15);
+  const int col = G * PW + jb * 16 + ord16<CT>(lane & 15);
   const int p = pl.p;
   const int ga = row / p, gb = col / p;
   if (ga != gb) return 0.0;
@@ -171,7 +210,7 @@ struct Coeff {
     if constexpr (Gm::BREG) {
       return r[c][(ab * NB + jb) * 4 + kk];
     } else {
-      return lds[c * PW * Gm::CST + coeff_row<T>(ab, kk, lane) * Gm::CST + jb * 16 + sigma16(lane & 15)];
+      return lds[c * PW * Gm::CST + coeff_row<T>(ab, kk, lane) * Gm::CST + jb * 16 + ord16<T>(lane & 15)];
     }
   }
 };
@@ -214,29 +253,92 @@ __device__ __forceinline__ double xch(double x) {
   return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
-// Pair layout of a 16 x 16 tile: lane l (s = l>>4, c = l&7, odd = bit 3)
-// holds columns 2c, 2c+1 of rows 4(2 odd + m) + s, m = 0, 1 (one 2-element
-// access per row). to_pairs converts a result tile with sigma-ordered columns
-// (element r: row 4r + s, column sigma(l&15) = 2c + odd) by one exchange of
-// two values between lanes l and l^8; from_pairs is its inverse and gives the
-// operand layout of the block products.
-template <typename T>
-__device__ __forceinline__ void to_pairs(const d4& D, T (&out)[2][2], bool odd) {
-  const T d0 = static_cast<T>(D[0]), d1 = static_cast<T>(D[1]);
-  const T d2 = static_cast<T>(D[2]), d3 = static_cast<T>(D[3]);
-  const T r0 = xch(odd ? d0 : d2), r1 = xch(odd ? d1 : d3);
-  out[0][0] = odd ? r0 : d0;
-  out[0][1] = odd ? d2 : r0;
-  out[1][0] = odd ? r1 : d1;
-  out[1][1] = odd ? d3 : r1;
+// 4 x 4 transpose among lanes l, l^4, l^8, l^12 (t = (l>>2)&3): in v[e] =
+// M[t][e], out w[m] = M[m][t] (three XOR swizzles within each 32 lanes).
+template <int D>
+__device__ __forceinline__ float xor4(float x) {
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), ((4 * D) << 10) | 0x1F));
 }
+__device__ __forceinline__ float pick4(const float (&v)[4], int i) {
+  return i == 0 ? v[0] : i == 1 ? v[1] : i == 2 ? v[2] : v[3];
+}
+__device__ __forceinline__ void transpose4(const float (&v)[4], float (&w)[4], int t) {
+  const float s1 = xor4<1>(pick4(v, t ^ 1)), s2 = xor4<2>(pick4(v, t ^ 2)), s3 = xor4<3>(pick4(v, t ^ 3));
+  const float own = pick4(v, t);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int d = m ^ t;
+    w[m] = d == 0 ? own : d == 1 ? s1 : d == 2 ? s2 : s3;
+  }
+}
+
+// Row layouts of a 16 x 16 tile for 2- or 4-element row accesses. A result
+// tile (element r: row 4r + s, s = l>>4, column ord16(l&15)) is converted by
+// to_rows and back, for the block products, by from_rows.
+//   FP64, pair layout: lane l (c = l&7, odd = bit 3) holds columns 2c, 2c+1
+//     of rows 4(2 odd + m) + s, m = 0, 1; one exchange of two values between
+//     lanes l and l^8 (sigma order: lanes l, l^8 hold adjacent columns).
+//   FP32, quad layout: lane l (c = l&3, t = (l>>2)&3) holds columns 4c..4c+3
+//     of row 4t + s; a 4 x 4 transpose among lanes l, l^4, l^8, l^12 (tau
+//     order: these lanes hold columns 4c..4c+3).
+// v[m * NC + e] is row slot m, column e.
 template <typename T>
-__device__ __forceinline__ void from_pairs(const T (&in)[2][2], double (&x)[4], bool odd) {
-  const T r0 = xch(odd ? in[0][0] : in[0][1]), r1 = xch(odd ? in[1][0] : in[1][1]);
-  x[0] = static_cast<double>(odd ? r0 : in[0][0]);
-  x[1] = static_cast<double>(odd ? r1 : in[1][0]);
-  x[2] = static_cast<double>(odd ? in[0][1] : r0);
-  x[3] = static_cast<double>(odd ? in[1][1] : r1);
+struct Lay;
+template <>
+struct Lay<double> {
+  static constexpr int NR = 2, NC = 2;
+  __device__ static int row(int m, int lane) { return 4 * (2 * ((lane >> 3) & 1) + m) + (lane >> 4); }
+  __device__ static int col(int lane) { return 2 * (lane & 7); }
+  __device__ static void load(const double* p, double* v) {
+    const double2 x = *reinterpret_cast<const double2*>(p);
+    v[0] = x.x;
+    v[1] = x.y;
+  }
+  __device__ static void store(double* p, const double* v) { *reinterpret_cast<double2*>(p) = double2{v[0], v[1]}; }
+};
+template <>
+struct Lay<float> {
+  static constexpr int NR = 1, NC = 4;
+  __device__ static int row(int, int lane) { return 4 * ((lane >> 2) & 3) + (lane >> 4); }
+  __device__ static int col(int lane) { return 4 * (lane & 3); }
+  __device__ static void load(const float* p, float* v) {
+    const float4 x = *reinterpret_cast<const float4*>(p);
+    v[0] = x.x;
+    v[1] = x.y;
+    v[2] = x.z;
+    v[3] = x.w;
+  }
+  __device__ static void store(float* p, const float* v) {
+    *reinterpret_cast<float4*>(p) = float4{v[0], v[1], v[2], v[3]};
+  }
+};
+
+__device__ __forceinline__ void to_rows(const d4& D, double (&v)[4], int lane) {
+  const bool odd = (lane >> 3) & 1;
+  const double r0 = xch(odd ? D[0] : D[2]), r1 = xch(odd ? D[1] : D[3]);
+  v[0] = odd ? r0 : D[0];
+  v[1] = odd ? D[2] : r0;
+  v[2] = odd ? r1 : D[1];
+  v[3] = odd ? D[3] : r1;
+}
+__device__ __forceinline__ void from_rows(const double (&v)[4], double (&x)[4], int lane) {
+  const bool odd = (lane >> 3) & 1;
+  const double r0 = xch(odd ? v[0] : v[1]), r1 = xch(odd ? v[2] : v[3]);
+  x[0] = odd ? r0 : v[0];
+  x[1] = odd ? r1 : v[2];
+  x[2] = odd ? v[1] : r0;
+  x[3] = odd ? v[3] : r1;
+}
+__device__ __forceinline__ void to_rows(const d4& D, float (&v)[4], int lane) {
+  const float d[4] = {static_cast<float>(D[0]), static_cast<float>(D[1]), static_cast<float>(D[2]),
+                      static_cast<float>(D[3])};
+  transpose4(d, v, (lane >> 2) & 3);
+}
+__device__ __forceinline__ void from_rows(const float (&v)[4], double (&x)[4], int lane) {
+  float w[4];
+  transpose4(v, w, (lane >> 2) & 3);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) x[r] = static_cast<double>(w[r]);
 }
 
 // Per-wave partial block products: result tiles per block pair.
@@ -317,30 +419,55 @@ constexpr int smem_doubles() {
 
 // ------------------------------------------------------------ R update
 // R -= Q lambda (line 9) and the partial <<R, R>> (line 11), whose diagonal
-// gives the column norms of the stop rule.
+// gives the column norms of the stop rule. FP32 with single-block groups:
+// the operands of the next tile are loaded before the products of the current
+// one (on the last tile of a wave the current tile is loaded again, from
+// cache); FP64 moves twice the bytes per product and gains nothing from it.
 template <typename T, int K, int PW>
 __global__ __launch_bounds__(kBlock) void k_update_r_mfma(Plan pl, T* __restrict__ R, const T* __restrict__ Q,
                                                           const T* __restrict__ lam, double* __restrict__ part,
                                                           const DevState* st) {
   if (mstopped(st)) return;
   using Gm = MGeo<K, PW>;
-  using T2 = typename V2m<T>::type;
+  using L = Lay<T>;
   constexpr int NB = Gm::NB;
   __shared__ double smem[smem_doubles<K, PW, 1>()];
-  const int lane = threadIdx.x & 63, s16 = lane >> 4, c2 = 2 * (lane & 7);
-  const bool odd = (lane >> 3) & 1;
+  const int lane = threadIdx.x & 63;
   const int64_t n = pl.n;
   const WaveWork ww = wave_work<Gm::NG>((n + 15) / 16);
   const int G = ww.group;
+  const int cbase = G * PW + L::col(lane);
   Coeff<T, K, PW, 1> cf;
   cf.load({lam}, {true}, pl, G, smem);
   MAcc<NB> acc;
   acc.zero();
+  double qa[NB][4];
+  T ra[NB][4];
+  auto load_rows = [&](int64_t t, int jb, T (&r)[4]) {
+#pragma unroll
+    for (int m = 0; m < L::NR; ++m) {
+      const int64_t row = min(t * 16 + L::row(m, lane), n - 1);
+      L::load(R + row * K + cbase + jb * 16, r + m * L::NC);
+    }
+  };
+  auto load_tile = [&](int64_t t, double (&q)[NB][4], T (&r)[NB][4]) {
+#pragma unroll
+    for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW>(q[ab], Q, t * 16, n, G, ab, lane);
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb) load_rows(t, jb, r[jb]);
+  };
+  constexpr bool PIPE = sizeof(T) == 4 && NB == 1;
+  if (PIPE && ww.first < ww.end) load_tile(ww.first, qa, ra);
   for (int64_t t = ww.first; t < ww.end; t += ww.stride) {
     const int64_t row0 = t * 16;
-    double qa[NB][4];
+    double qn[NB][4];
+    T rnx[NB][4];
+    if constexpr (PIPE) {
+      load_tile(t + ww.stride < ww.end ? t + ww.stride : t, qn, rnx);
+    } else {
 #pragma unroll
-    for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW>(qa[ab], Q, row0, n, G, ab, lane);
+      for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW>(qa[ab], Q, row0, n, G, ab, lane);
+    }
     double rn[NB][4];
 #pragma unroll
     for (int jb = 0; jb < NB; ++jb) {
@@ -349,32 +476,38 @@ __global__ __launch_bounds__(kBlock) void k_update_r_mfma(Plan pl, T* __restrict
       for (int ab = 0; ab < NB; ++ab)
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) D = mfma(qa[ab][kk], cf.b(0, ab, jb, kk, lane), D);
-      T dq[2][2], rv[2][2];
-      to_pairs<T>(D, dq, odd);
+      if constexpr (!PIPE) load_rows(t, jb, ra[jb]);
+      T dq[4], rv[4];
+      to_rows(D, dq, lane);
 #pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        const int64_t row = row0 + 4 * (2 * odd + m) + s16;
-        rv[m][0] = rv[m][1] = T(0);
-        if (row < n) {
-          T2* ptr = reinterpret_cast<T2*>(R + row * K + G * PW + jb * 16 + c2);
-          T2 r = *ptr;
-          r.x = r.x - dq[m][0];  // R - Q lambda
-          r.y = r.y - dq[m][1];
-          *ptr = r;
-          rv[m][0] = r.x;
-          rv[m][1] = r.y;
-        }
+      for (int m = 0; m < L::NR; ++m) {
+        const int64_t row = row0 + L::row(m, lane);
+        const bool ok = row < n;
+        T* v = rv + m * L::NC;
+#pragma unroll
+        for (int e = 0; e < L::NC; ++e) v[e] = ok ? ra[jb][m * L::NC + e] - dq[m * L::NC + e] : T(0);  // R - Q lambda
+        if (ok) L::store(R + row * K + cbase + jb * 16, v);
       }
-      from_pairs<T>(rv, rn[jb], odd);
+      from_rows(rv, rn[jb], lane);
     }
     gram_tiles<NB>(acc, rn, rn);
+    if constexpr (PIPE)
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          qa[jb][e] = qn[jb][e];
+          ra[jb][e] = rnx[jb][e];
+        }
   }
-  finish_mfma<K, PW, true>(acc, G, smem, part + (int64_t)blockIdx.x * pl.W, pl);
+  finish_mfma<K, PW, true, perm_of<T>()>(acc, G, smem, part + (int64_t)blockIdx.x * pl.W, pl);
 }
 
 // ------------------------------------------------------- X and P update
 // X += P lambda (line 8); unless `last`: P = R + P beta (line 13) and the
-// partial rho = <<P_new, R>> of the next iteration's line 6.
+// partial rho = <<P_new, R>> of the next iteration's line 6. FP32 with
+// single-block groups: operands of the next tile are loaded before the
+// products of the current one.
 template <typename T, int K, int PW>
 __global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restrict__ X, T* __restrict__ Pm,
                                                            const T* __restrict__ R, const T* __restrict__ lam,
@@ -383,23 +516,46 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restric
   if (mstopped(st)) return;
   const bool last = *reinterpret_cast<const volatile int*>(&st->last) != 0;
   using Gm = MGeo<K, PW>;
-  using T2 = typename V2m<T>::type;
+  using L = Lay<T>;
   constexpr int NB = Gm::NB;
   __shared__ double smem[smem_doubles<K, PW, 2>()];
-  const int lane = threadIdx.x & 63, s16 = lane >> 4, c2 = 2 * (lane & 7);
-  const bool odd = (lane >> 3) & 1;
+  const int lane = threadIdx.x & 63;
   const int64_t n = pl.n;
   const WaveWork ww = wave_work<Gm::NG>((n + 15) / 16);
   const int G = ww.group;
+  const int cbase = G * PW + L::col(lane);
   Coeff<T, K, PW, 2> cf;
   cf.load({lam, beta}, {true, !last}, pl, G, smem);
   MAcc<NB> acc;
   acc.zero();
+  double pa[NB][4];
+  T xa[NB][4], ra[NB][4];
+  auto load_rows = [&](int64_t t, int jb, T (&x)[4], T (&r)[4]) {
+#pragma unroll
+    for (int m = 0; m < L::NR; ++m) {
+      const int64_t off = min(t * 16 + L::row(m, lane), n - 1) * K + cbase + jb * 16;
+      L::load(X + off, x + m * L::NC);
+      if (!last) L::load(R + off, r + m * L::NC);
+    }
+  };
+  auto load_tile = [&](int64_t t, double (&pq)[NB][4], T (&x)[NB][4], T (&r)[NB][4]) {
+#pragma unroll
+    for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW>(pq[ab], Pm, t * 16, n, G, ab, lane);
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb) load_rows(t, jb, x[jb], r[jb]);
+  };
+  constexpr bool PIPE = sizeof(T) == 4 && NB == 1;
+  if (PIPE && ww.first < ww.end) load_tile(ww.first, pa, xa, ra);
   for (int64_t t = ww.first; t < ww.end; t += ww.stride) {
     const int64_t row0 = t * 16;
-    double pa[NB][4];
+    double pnx[NB][4];
+    T xnx[NB][4], rnx[NB][4];
+    if constexpr (PIPE) {
+      load_tile(t + ww.stride < ww.end ? t + ww.stride : t, pnx, xnx, rnx);
+    } else {
 #pragma unroll
-    for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW>(pa[ab], Pm, row0, n, G, ab, lane);
+      for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW>(pa[ab], Pm, row0, n, G, ab, lane);
+    }
     double pn[NB][4], rd[NB][4];
 #pragma unroll
     for (int jb = 0; jb < NB; ++jb) {
@@ -408,47 +564,51 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restric
       for (int ab = 0; ab < NB; ++ab)
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) Dx = mfma(pa[ab][kk], cf.b(0, ab, jb, kk, lane), Dx);
-      T dx[2][2], dp[2][2], pv[2][2], rv[2][2];
-      to_pairs<T>(Dx, dx, odd);
+      if constexpr (!PIPE) load_rows(t, jb, xa[jb], ra[jb]);
+      T dx[4], dp[4], pv[4], rv[4];
+      to_rows(Dx, dx, lane);
       if (!last) {
 #pragma unroll
         for (int ab = 0; ab < NB; ++ab)
 #pragma unroll
           for (int kk = 0; kk < 4; ++kk) Dp = mfma(pa[ab][kk], cf.b(1, ab, jb, kk, lane), Dp);
-        to_pairs<T>(Dp, dp, odd);
+        to_rows(Dp, dp, lane);
       }
 #pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        const int64_t row = row0 + 4 * (2 * odd + m) + s16;
-        pv[m][0] = pv[m][1] = rv[m][0] = rv[m][1] = T(0);
-        if (row < n) {
-          const int64_t off = row * K + G * PW + jb * 16 + c2;
-          T2* xp = reinterpret_cast<T2*>(X + off);
-          T2 x = *xp;
-          x.x = x.x + dx[m][0];  // X + P lambda
-          x.y = x.y + dx[m][1];
-          *xp = x;
-          if (!last) {
-            const T2 r = *reinterpret_cast<const T2*>(R + off);
-            T2 pnew;
-            pnew.x = r.x + dp[m][0];  // R + P beta
-            pnew.y = r.y + dp[m][1];
-            *reinterpret_cast<T2*>(Pm + off) = pnew;
-            pv[m][0] = pnew.x;
-            pv[m][1] = pnew.y;
-            rv[m][0] = r.x;
-            rv[m][1] = r.y;
-          }
+      for (int m = 0; m < L::NR; ++m) {
+        const int64_t row = row0 + L::row(m, lane);
+        const bool ok = row < n;
+        const int64_t off = row * K + cbase + jb * 16;
+        T x[L::NC];
+#pragma unroll
+        for (int e = 0; e < L::NC; ++e) x[e] = xa[jb][m * L::NC + e] + dx[m * L::NC + e];  // X + P lambda
+        if (ok) L::store(X + off, x);
+        T* pvm = pv + m * L::NC;
+        T* rvm = rv + m * L::NC;
+#pragma unroll
+        for (int e = 0; e < L::NC; ++e) {
+          rvm[e] = (ok && !last) ? ra[jb][m * L::NC + e] : T(0);
+          pvm[e] = (ok && !last) ? rvm[e] + dp[m * L::NC + e] : T(0);  // R + P beta
         }
+        if (ok && !last) L::store(Pm + off, pvm);
       }
       if (!last) {
-        from_pairs<T>(pv, pn[jb], odd);
-        from_pairs<T>(rv, rd[jb], odd);
+        from_rows(pv, pn[jb], lane);
+        from_rows(rv, rd[jb], lane);
       }
     }
     if (!last) gram_tiles<NB>(acc, pn, rd);  // rho = <<P_new, R>>
+    if constexpr (PIPE)
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          pa[jb][e] = pnx[jb][e];
+          xa[jb][e] = xnx[jb][e];
+          ra[jb][e] = rnx[jb][e];
+        }
   }
-  finish_mfma<K, PW, false>(acc, G, smem, part + (int64_t)blockIdx.x * pl.W, pl);
+  finish_mfma<K, PW, false, perm_of<T>()>(acc, G, smem, part + (int64_t)blockIdx.x * pl.W, pl);
 }
 
 // ---------------------------------------------------------------- SpMM
@@ -525,7 +685,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __
   const int lane = threadIdx.x & 63, rr = lane >> 3, cg = lane & 7;
   const bool odd = (lane >> 3) & 1;
   const int64_t n = pl.n;
-  const WaveWork ww = wave_work<Gm::NG>((n + 7) / 8);
+  const WaveWork ww = wave_work_sp<Gm::NG>((n + 7) / 8, pl.sp_chunk[0]);
   const int G = ww.group;
   const int c0 = G * PW + 2 * cg;
   MAcc<NB> acc;
@@ -667,22 +827,12 @@ template <int I>
 __device__ __forceinline__ float quad_bcast(float x) {
   return __int_as_float(quad_bcast<I>(__float_as_int(x)));
 }
-template <int D>
-__device__ __forceinline__ float xor4(float x) {
-  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), ((4 * D) << 10) | 0x1F));
-}
-__device__ __forceinline__ float pick4(const float (&v)[4], int i) {
-  return i == 0 ? v[0] : i == 1 ? v[1] : i == 2 ? v[2] : v[3];
-}
-// in v[e] = X[row t][e], out w[m] = X[row m][t] within the 4 lanes (t = (l>>2)&3)
+// in v[e] = X[row t][e], out w[m] = X[row m][t] as FP64 operands
 __device__ __forceinline__ void transpose4(const float (&v)[4], double (&w)[4], int t) {
-  const float s1 = xor4<1>(pick4(v, t ^ 1)), s2 = xor4<2>(pick4(v, t ^ 2)), s3 = xor4<3>(pick4(v, t ^ 3));
-  const float own = pick4(v, t);
+  float f[4];
+  transpose4(v, f, t);
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int d = m ^ t;
-    w[m] = static_cast<double>(d == 0 ? own : d == 1 ? s1 : d == 2 ? s2 : s3);
-  }
+  for (int m = 0; m < 4; ++m) w[m] = static_cast<double>(f[m]);
 }
 
 struct Row8f {
@@ -712,7 +862,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma_f32(Plan pl, const int32_t
   __shared__ double smem[smem_doubles<K, PW, 0>()];
   const int lane = threadIdx.x & 63, rr = lane >> 2, cq = lane & 3, tq = (lane >> 2) & 3;
   const int64_t n = pl.n;
-  const WaveWork ww = wave_work<Gm::NG>((n + 15) / 16);
+  const WaveWork ww = wave_work_sp<Gm::NG>((n + 15) / 16, pl.sp_chunk[1]);
   const int G = ww.group;
   const int c0 = G * PW + 4 * cq;
   MAcc<NB> acc;
@@ -897,6 +1047,38 @@ int mfma_width(int64_t nnz, int k, int p) {
   return 0;
 }
 
+void mfma_sp_grid(Plan& pl) {
+  const int w = pl.mfma, ng = pl.k / w;
+  const bool share = ng <= 4 && 4 % ng == 0;
+  const int ngb = share ? 1 : (ng + 3) / 4, wpg = share ? 4 / ng : 1;
+  const int kwg = share ? pl.k : 4 * w;  // columns one workgroup covers
+  const char* env = std::getenv("BCG_SP_CHUNK");
+  for (int prec = 0; prec < 2; ++prec) {
+    const int rows_step = prec ? 16 : 8, elem = prec ? 4 : 8;
+    const int64_t nsteps = (pl.n + rows_step - 1) / rows_step;
+    // steps per wave: a workgroup's partial row (8 W bytes) at most 1/32 of
+    // the bytes its chunk moves
+    const double step_bytes = static_cast<double>(wpg) * rows_step * (2.0 * kwg * elem + 12.0);
+    int chunk = static_cast<int>(std::ceil(256.0 * pl.W / step_bytes));
+    if (chunk < 8) chunk = 8;
+    if (env) chunk = std::atoi(env);
+    if (chunk <= 0) {
+      pl.sp_chunk[prec] = 0;
+      pl.sp_nwg[prec] = pl.nwg;
+      continue;
+    }
+    const int64_t per = (nsteps + 7) / 8;
+    int64_t span = static_cast<int64_t>(chunk) * wpg, nch = (per + span - 1) / span;
+    while (8 * ngb * nch > kMaxSpWG) {
+      chunk *= 2;
+      span = static_cast<int64_t>(chunk) * wpg;
+      nch = (per + span - 1) / span;
+    }
+    pl.sp_chunk[prec] = chunk;
+    pl.sp_nwg[prec] = static_cast<int>(8 * ngb * nch);
+  }
+}
+
 int mfma_grid(int64_t n, int k, int w) {
   const int64_t ng = k / w;
   const int64_t units = ((n + 15) / 16) * ng;
@@ -913,14 +1095,16 @@ int mfma_grid(int64_t n, int k, int w) {
 template <typename T>
 void launch_spmm_mfma(const Plan& pl, const int32_t* rowptr, const int32_t* colind, const T* vals, const T* P, T* Q,
                       double* part, const DevState* st, hipStream_t s) {
-  check_grid(pl);
+  const int prec = std::is_same<T, float>::value ? 1 : 0;
+  if (pl.sp_chunk[prec] == 0) check_grid(pl);
+  const dim3 grid(pl.sp_nwg[prec]);
   dispatch_mfma(pl, [&](auto Kc, auto Wc) {
     if constexpr (std::is_same<T, float>::value)
-      hipLaunchKernelGGL((k_spmm_mfma_f32<decltype(Kc)::value, decltype(Wc)::value>), dim3(pl.nwg), dim3(kBlock), 0,
-                         s, pl, rowptr, colind, vals, P, Q, part, st);
+      hipLaunchKernelGGL((k_spmm_mfma_f32<decltype(Kc)::value, decltype(Wc)::value>), grid, dim3(kBlock), 0, s, pl,
+                         rowptr, colind, vals, P, Q, part, st);
     else
-      hipLaunchKernelGGL((k_spmm_mfma<T, decltype(Kc)::value, decltype(Wc)::value>), dim3(pl.nwg), dim3(kBlock), 0,
-                         s, pl, rowptr, colind, vals, P, Q, part, st);
+      hipLaunchKernelGGL((k_spmm_mfma<T, decltype(Kc)::value, decltype(Wc)::value>), grid, dim3(kBlock), 0, s, pl,
+                         rowptr, colind, vals, P, Q, part, st);
   });
 }
 

@@ -16,6 +16,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/bcg.h"
@@ -100,6 +101,7 @@ struct bcg_handle {
   float* vals32 = nullptr;
   double *R = nullptr, *P = nullptr, *Q = nullptr;
   double *partA = nullptr, *partR = nullptr, *partN = nullptr;
+  double* part2 = nullptr;  // first-stage rows of reductions over many partial rows
   double *alpha = nullptr, *rho = nullptr, *rnew = nullptr;
   double *lam = nullptr, *beta = nullptr, *ws = nullptr;
   float *lam32 = nullptr, *beta32 = nullptr;
@@ -133,7 +135,7 @@ struct bcg_handle {
 namespace {
 
 void free_all(bcg_handle* h) {
-  void* ptrs[] = {h->rowptr, h->colind, h->vals, h->vals32, h->R, h->P, h->Q, h->partA, h->partR, h->partN,
+  void* ptrs[] = {h->rowptr, h->colind, h->vals, h->vals32, h->R, h->P, h->Q, h->partA, h->part2, h->partR, h->partN,
                   h->alpha, h->rho, h->rnew, h->lam, h->beta, h->ws, h->lam32, h->beta32, h->r0, h->ratios,
                   h->scale, h->st, h->R32, h->P32, h->Q32, h->D32, h->sched};
   for (void* p : ptrs)
@@ -238,7 +240,8 @@ void enqueue_iteration(bcg_handle* h, const IterBuffers<T>& b, double tol, int i
       launch_spmm_product<T>(pl, h->rowptr, h->colind, b.vals, b.P, b.Q, h->partA, h->st, s);
   });
   if (!fast && !pl.fused) timed(h, BCG_K_PRODUCT, it, [&] { launch_product<T>(pl, b.P, b.Q, h->partA, h->st, s); });
-  timed(h, BCG_K_REDUCE, it, [&] { launch_reduce(pl, h->partA, h->alpha, pl.E, h->st, s); });
+  const int sp_rows = mfma ? pl.sp_nwg[std::is_same<T, float>::value ? 1 : 0] : pl.nwg;
+  timed(h, BCG_K_REDUCE, it, [&] { launch_reduce(pl, h->partA, h->alpha, pl.E, h->st, s, 0, sp_rows, h->part2); });
   timed(h, BCG_K_SMALL, it, [&] {  // line 7
     launch_solve_lambda(pl, h->alpha, h->rho, h->lam, h->lam32, h->ws, h->st, s);
   });
@@ -552,10 +555,12 @@ int bcg_create(const bcg_csr* A, int k, int subalgebra, int p, bcg_handle** out)
   const Plan& pl = h->pl;
   const size_t nk = static_cast<size_t>(h->n) * k;
   const size_t partsz = static_cast<size_t>(pl.nwg) * pl.W;
+  const size_t partasz = static_cast<size_t>(std::max({pl.nwg, pl.sp_nwg[0], pl.sp_nwg[1]})) * pl.W;
   const size_t wssz = (pl.p > 48) ? static_cast<size_t>(pl.qo) * 2 * pl.p * pl.p : 1;
   if ((rc = dalloc(&h->rowptr, h->n + 1)) || (rc = dalloc(&h->colind, h->nnz)) || (rc = dalloc(&h->vals, h->nnz)) ||
       (rc = dalloc(&h->vals32, h->nnz)) || (rc = dalloc(&h->R, nk)) || (rc = dalloc(&h->P, nk)) ||
-      (rc = dalloc(&h->Q, nk)) || (rc = dalloc(&h->partA, partsz)) || (rc = dalloc(&h->partR, partsz)) ||
+      (rc = dalloc(&h->Q, nk)) || (rc = dalloc(&h->partA, partasz)) ||
+      (rc = dalloc(&h->part2, static_cast<size_t>(kRedSplits) * pl.W)) || (rc = dalloc(&h->partR, partsz)) ||
       (rc = dalloc(&h->partN, partsz)) || (rc = dalloc(&h->alpha, pl.W)) || (rc = dalloc(&h->rho, pl.W)) ||
       (rc = dalloc(&h->rnew, pl.W)) || (rc = dalloc(&h->lam, pl.E)) || (rc = dalloc(&h->beta, pl.E)) ||
       (rc = dalloc(&h->lam32, pl.E)) || (rc = dalloc(&h->beta32, pl.E)) || (rc = dalloc(&h->ws, wssz)) ||

@@ -367,3 +367,24 @@ def test_row_schedule_rejects_out_of_range():
     Xo, _ = oracle_solve(A, B, "block", 0, tol=0.0, maxit=5)
     Xg, _ = s.solve(dev(B), tol=0.0, maxit=5)      # still the natural order
     assert rel(host(Xg), Xo) <= FIXED_TOL
+
+
+# ------------------------------------------ full-size launch configuration
+@pytest.mark.parametrize("variant,p,order", [("block", 0, "natural"), ("block", 0, "tiled"), ("hybrid", 4, "tiled")])
+def test_full_size_poisson3d_128_fixed_iterations(variant, p, order):
+    """128^3 Poisson, k = 16: the chunked sparse-product grid and the two-stage
+    reduction of its partial products at the benchmark's size, 6 iterations."""
+    P = _lib()
+    w = WORKLOADS["poisson3d_128_k16"]
+    log(f"full size {variant} p={p} {order}")
+    A = stencil_csr(w.dim, w.N)
+    B = rhs_for(w)
+    m = 6
+    Xo, io = oracle_solve(A, B, variant, p, tol=0.0, maxit=m)
+    s = P.BCG(*P.stencil(w.dim, w.N), k=w.k, subalgebra=variant, p=p)
+    if order == "tiled":
+        s.set_row_schedule(P.stencil_schedule(w.dim, w.N, 32))
+    Xg, ig = s.solve(dev(B), tol=0.0, maxit=m)
+    assert ig["iterations"] == io["iterations"] == m
+    assert rel(host(Xg), Xo) <= FIXED_TOL
+    np.testing.assert_allclose(ig["ratios"], io["ratios"], rtol=1e-8, atol=0)
