@@ -1052,7 +1052,6 @@ void mfma_sp_grid(Plan& pl) {
   const bool share = ng <= 4 && 4 % ng == 0;
   const int ngb = share ? 1 : (ng + 3) / 4, wpg = share ? 4 / ng : 1;
   const int kwg = share ? pl.k : 4 * w;  // columns one workgroup covers
-  const char* env = std::getenv("BCG_SP_CHUNK");
   for (int prec = 0; prec < 2; ++prec) {
     const int rows_step = prec ? 16 : 8, elem = prec ? 4 : 8;
     const int64_t nsteps = (pl.n + rows_step - 1) / rows_step;
@@ -1061,12 +1060,6 @@ void mfma_sp_grid(Plan& pl) {
     const double step_bytes = static_cast<double>(wpg) * rows_step * (2.0 * kwg * elem + 12.0);
     int chunk = static_cast<int>(std::ceil(256.0 * pl.W / step_bytes));
     if (chunk < 8) chunk = 8;
-    if (env) chunk = std::atoi(env);
-    if (chunk <= 0) {
-      pl.sp_chunk[prec] = 0;
-      pl.sp_nwg[prec] = pl.nwg;
-      continue;
-    }
     const int64_t per = (nsteps + 7) / 8;
     int64_t span = static_cast<int64_t>(chunk) * wpg, nch = (per + span - 1) / span;
     while (8 * ngb * nch > kMaxSpWG) {
