@@ -102,15 +102,20 @@ def _pmc_means(db_path: str, counter: str) -> dict:
     for name, vals in per.items():
         top = max(vals)
         work = [v for v in vals if v > 0.01 * top]  # launches that returned at entry are dropped
-        out[name] = sum(work) / len(work)
+        out[name] = sum(work) / len(work) if work else 0.0
     return out
 
 
-def traffic_from(directory: str, workload: str, variant: str, precision: str) -> int:
+def _is_fp32_kernel(name: str) -> bool:
+    return "_f32" in name or "<float" in name
+
+
+def traffic_from(directory: str, workload: str, variant: str) -> int:
     """Write profiles/traffic.json from four rocprofv3 --pmc databases under
     `directory`: copy_fetch, copy_write (bench.py --copy-calibration) and
-    fetch, write (the benchmark). FETCH_SIZE / WRITE_SIZE are KiB per dispatch;
-    each is scaled so that the plain copy reads and writes COPY_BYTES."""
+    fetch, write (the benchmark, both precisions). FETCH_SIZE / WRITE_SIZE are
+    KiB per dispatch; each is scaled so that the plain copy reads and writes
+    COPY_BYTES."""
     import glob
 
     def db(sub):
@@ -126,18 +131,22 @@ def traffic_from(directory: str, workload: str, variant: str, precision: str) ->
     write = _pmc_means(db("write"), "WRITE_SIZE")
     path = os.path.join(ROOT, "profiles", "traffic.json")
     rec = json.load(open(path)) if os.path.exists(path) else {}
-    for cls, knames in KERNEL_NAMES.items():
-        fk = [v for n, v in fetch.items() if any(kn in n for kn in knames)]
-        wk = [v for n, v in write.items() if any(kn in n for kn in knames)]
-        if not fk or not wk:
-            continue
-        rd = fk[0] * 1024 * f_fetch
-        wr = wk[0] * 1024 * f_write
-        rec[f"{cls}/{workload}/{variant}/{precision}"] = {
-            "bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr,
-            "fetch_kib": fk[0], "write_kib": wk[0], "fetch_scale": f_fetch, "write_scale": f_write,
-            "kernel_hash": kernel_hash(),
-        }
+    for precision in ("fp64", "fp32_refine"):
+        want32 = precision != "fp64"
+        for cls, knames in KERNEL_NAMES.items():
+            def pick(table):
+                return [v for nm, v in table.items()
+                        if any(kn in nm for kn in knames) and _is_fp32_kernel(nm) == want32]
+            fk, wk = pick(fetch), pick(write)
+            if not fk or not wk:
+                continue
+            rd = fk[0] * 1024 * f_fetch
+            wr = wk[0] * 1024 * f_write
+            rec[f"{cls}/{workload}/{variant}/{precision}"] = {
+                "bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr,
+                "fetch_kib": fk[0], "write_kib": wk[0], "fetch_scale": f_fetch, "write_scale": f_write,
+                "kernel_hash": kernel_hash(),
+            }
     with open(path, "w") as fh:
         json.dump(rec, fh, indent=1, sort_keys=True)
     print(json.dumps(rec, indent=1, sort_keys=True))
@@ -187,11 +196,13 @@ def main() -> int:
     ap.add_argument("--workload", default="poisson3d_128_k16")
     ap.add_argument("--variant", default="block")
     ap.add_argument("--p", type=int, default=0)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_refine"])
+    ap.add_argument("--precision", default="fp32_refine", choices=["fp64", "fp32_refine"],
+                    help="precision of the headline solve; the other form is timed beside it")
+    ap.add_argument("--no-compare", action="store_true", help="skip the solve in the other precision")
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--schedule", default="natural", choices=["tiled", "natural"],
+    ap.add_argument("--schedule", default="tiled", choices=["tiled", "natural"],
                     help="row order of the sparse product: 32x32 x-y tiles swept through z (3D), or natural")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (counter calibration)")
@@ -201,7 +212,7 @@ def main() -> int:
     if args.copy_calibration:
         return copy_calibration()
     if args.traffic_from:
-        return traffic_from(args.traffic_from, args.workload, args.variant, args.precision)
+        return traffic_from(args.traffic_from, args.workload, args.variant)
 
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1",
@@ -209,7 +220,6 @@ def main() -> int:
         log("bench.py: only --gpus 1 is supported; the library has no multi-GPU path")
         return 2
 
-    import numpy as np
     import torch
 
     import paper_1912_11930_amd as P
@@ -228,57 +238,61 @@ def main() -> int:
     if args.schedule == "tiled" and w.dim == 3:
         solver.set_row_schedule(P.stencil_schedule(w.dim, w.N, 32, device=dev))
         schedule = "tiled 32x32 (x,y) swept through z"
-    if args.precision != "fp64":
-        solver.set_precision(args.precision)
     p_eff = {"block": k, "parallel": 1}.get(args.variant, args.p or 1)
-    X = torch.empty_like(B)
     torch.cuda.synchronize()
-    log(f"bench: {w.name} n={n} nnz={nnz} k={k} variant={args.variant} p={p_eff} precision={args.precision}")
 
-    # warm-up solves; the last one profiles every kernel class for the breakdown
-    info = None
-    for i in range(max(args.warmup, 1)):
-        if i == max(args.warmup, 1) - 1:
-            solver.set_profiling(True)
-        X.zero_()
-        _, info = solver.solve(B, X, tol=tol, maxit=100000)
-        log(f"warmup {i}: status={info['status_name']} iterations={info['iterations']} "
-            f"{info['solve_ms']:.1f} ms true_rel_res={info['true_rel_res']:.2e}")
-    breakdown = solver.kernel_times()
-    solver.set_profiling(False)
-    cand = {c: breakdown[c][1] for c in ("spmm", "update_r", "update_xp")}
-    dominant = max(cand, key=cand.get)
+    def run(precision: str, steps: int, warmup: int) -> dict:
+        """Warm-up solves (the last one profiles every kernel class), then
+        `steps` timed solves with events only around the dominant class."""
+        solver.set_precision(precision)
+        X = torch.empty_like(B)
+        log(f"bench: {w.name} n={n} nnz={nnz} k={k} variant={args.variant} p={p_eff} precision={precision}")
+        info = None
+        for i in range(max(warmup, 1)):
+            if i == max(warmup, 1) - 1:
+                solver.set_profiling(True)
+            X.zero_()
+            _, info = solver.solve(B, X, tol=tol, maxit=100000)
+            log(f"warmup {i}: status={info['status_name']} iterations={info['iterations']} "
+                f"{info['solve_ms']:.1f} ms true_rel_res={info['true_rel_res']:.2e}")
+        breakdown = solver.kernel_times()
+        solver.set_profiling(False)
+        cand = {c: breakdown[c][1] for c in ("spmm", "update_r", "update_xp")}
+        dominant = max(cand, key=cand.get)
+        solver.set_profiling(True, classes=[dominant])
+        its = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            X.zero_()
+            _, info = solver.solve(B, X, tol=tol, maxit=100000)
+            its.append(info["iterations"])
+            log(f"step {i}: status={info['status_name']} iterations={info['iterations']} "
+                f"{info['solve_ms']:.1f} ms")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        launches, total_ms = solver.kernel_times()[dominant]
+        solver.set_profiling(False)
+        kernels = {c: {"launches": breakdown[c][0], "total_ms": round(breakdown[c][1], 3),
+                       "avg_us": round(1e3 * breakdown[c][1] / max(breakdown[c][0], 1), 2)}
+                   for c in _capi.KERNEL_CLASSES if breakdown[c][0]}
+        for c in ("spmm", "update_r", "update_xp"):
+            if c in kernels:
+                bts = algorithmic_bytes(c, n, nnz, k, precision)
+                kernels[c]["GBps"] = round(bts / (kernels[c]["avg_us"] * 1e-6) / 1e9, 1)
+        return {"precision": precision, "elapsed": elapsed, "steps": steps, "X": X, "info": info,
+                "iterations": its[-1] if its else None, "dominant": dominant, "launches": launches,
+                "avg_ms": total_ms / max(launches, 1), "kernels": kernels,
+                "kernels_total_ms": round(sum(v[1] for v in breakdown.values()), 3)}
 
-    # timed region: events only around the dominant kernel class
-    solver.set_profiling(True, classes=[dominant])
-    its = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        X.zero_()
-        _, info = solver.solve(B, X, tol=tol, maxit=100000)
-        its.append(info["iterations"])
-        log(f"step {i}: status={info['status_name']} iterations={info['iterations']} {info['solve_ms']:.1f} ms")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    launches, total_ms = solver.kernel_times()[dominant]
-    solver.set_profiling(False)
-
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = k * args.steps / elapsed
-    avg_ms = total_ms / max(launches, 1)
+    head = run(args.precision, args.steps, args.warmup)
+    ms_per_step = 1e3 * head["elapsed"] / args.steps
+    value = k * args.steps / head["elapsed"]
+    dominant = head["dominant"]
     bytes_launch = algorithmic_bytes(dominant, n, nnz, k, args.precision)
-    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    achieved = bytes_launch / (head["avg_ms"] * 1e-3) / 1e9
     traffic = measured_traffic(dominant, w.name, args.variant, args.precision)
-
-    total_known = sum(v[1] for v in breakdown.values())
-    kernels = {c: {"launches": breakdown[c][0], "total_ms": round(breakdown[c][1], 3),
-                   "avg_us": round(1e3 * breakdown[c][1] / max(breakdown[c][0], 1), 2)}
-               for c in _capi.KERNEL_CLASSES if breakdown[c][0]}
-    for c in ("spmm", "update_r", "update_xp"):
-        if c in kernels:
-            b = algorithmic_bytes(c, n, nnz, k, args.precision)
-            kernels[c]["GBps"] = round(b / (kernels[c]["avg_us"] * 1e-6) / 1e9, 1)
+    info = head["info"]
 
     out = {
         "metric": METRIC,
@@ -296,21 +310,46 @@ def main() -> int:
         "config": {"workload": w.name, "grid": f"{w.N}^{w.dim}", "n": n, "nnz": nnz, "k": k,
                    "variant": args.variant, "p": p_eff, "precision": args.precision, "tol": tol,
                    "rhs": w.rhs, "row_schedule": schedule},
-        "iterations": its[-1] if its else None,
+        "iterations": head["iterations"],
+        "outer_iterations": info["outer_iterations"] if info else None,
         "true_rel_res": info["true_rel_res"] if info else None,
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "bytes_per_launch": bytes_launch, "avg_launch_us": 1e3 * avg_ms,
-                     "launches": launches},
-        "kernels": kernels,
-        "kernels_total_ms": round(total_known, 3),
+                     "bytes_per_launch": bytes_launch, "avg_launch_us": 1e3 * head["avg_ms"],
+                     "launches": head["launches"]},
+        "kernels": head["kernels"],
+        "kernels_total_ms": head["kernels_total_ms"],
         "cpu_baseline": None,
     }
+    if not args.no_compare:
+        other = "fp64" if args.precision != "fp64" else "fp32_refine"
+        cmp_ = run(other, args.steps, 1)
+        diff = float(torch.linalg.norm(head["X"] - cmp_["X"]) / torch.linalg.norm(cmp_["X"]))
+        out["compare"] = {
+            "precision": other,
+            "value": k * args.steps / cmp_["elapsed"],
+            "ms_per_step": 1e3 * cmp_["elapsed"] / args.steps,
+            "iterations": cmp_["iterations"],
+            "true_rel_res": cmp_["info"]["true_rel_res"],
+            "speedup_of_headline": (k * args.steps / head["elapsed"]) / (k * args.steps / cmp_["elapsed"]),
+            "rel_diff_solutions": diff,
+            "kernels": cmp_["kernels"],
+        }
     if not args.no_cpu_baseline:
         log("cpu_baseline: timing the oracle ...")
-        out["cpu_baseline"] = cpu_baseline(w, args.variant, p_eff, its[-1] if its else 1, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(w, args.variant, p_eff, head_fp64_iterations(out), args.cpu_budget)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def head_fp64_iterations(out: dict) -> int:
+    """FP64 iteration count of the benchmark solve (the oracle runs FP64)."""
+    if out["config"]["precision"] == "fp64":
+        return out["iterations"] or 1
+    cmp_ = out.get("compare")
+    if cmp_ and cmp_["precision"] == "fp64":
+        return cmp_["iterations"] or 1
+    return out["iterations"] or 1
 
 
 if __name__ == "__main__":
