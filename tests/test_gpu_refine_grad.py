@@ -140,14 +140,16 @@ def test_sampled_outer_and_solve_gradient_dense():
 def test_fd_check_diffusion2d_512():
     """Adjoint gradient vs central differences on 64 coefficients (512^2, k = 32).
 
-    Forward and adjoint solves at tol 1e-12; each +/- pair runs the
-    unperturbed iteration count + 5 in fixed-iteration mode (a smooth map);
-    the difference of the two solutions is formed before the loss sum.
-    Tolerance: 1e-5 * (|g| + max|g|). The difference quotient carries the
-    rounding noise of two ~700-iteration solves divided by 2h = 2e-6, about
-    3e-6 of the gradient's scale here, so a bound relative to each component
-    alone is not attainable for the small components; a wrong derivative
-    (sign, transpose, missing face) is off by O(1) of the scale.
+    Forward and adjoint solves at tol 1e-13; each +/- h pair runs the
+    unperturbed iteration count + 5 in fixed-iteration mode (a smooth map of
+    the coefficients); the difference of the two solutions is formed before
+    the loss sum. With the step h = 1e-6 of this workload the difference
+    quotient carries the attainable-accuracy floor of the solves (true
+    relative residual ~4e-13 even when asked for 1e-14) divided by 2h:
+    measured 1.5e-6 median and 7e-6 to 9.4e-6 worst of |fd - ad| / (|ad| +
+    max|ad|) over the 64 coefficients (block or parallel difference solves,
+    tol 1e-12 to 1e-14). Tolerance 3e-5; a wrong derivative (sign, transpose,
+    missing face) is off by O(1) of the gradient's scale.
     """
     P = _P()
     w = WORKLOADS["diffusion2d_512_k32"]
@@ -160,7 +162,7 @@ def test_fd_check_diffusion2d_512():
     rp, ci, v0 = P.stencil(dim, N, kt.detach())
     s = P.BCG(rp, ci, v0, k=k, subalgebra="block")
     vals = P.StencilValues.apply(kt, dim, N)
-    X = P.BCGSolve.apply(vals, B, s, 1e-12, 100000)
+    X = P.BCGSolve.apply(vals, B, s, 1e-13, 100000)
     its = s.info()["iterations"]
     (W * X).sum().backward()
     g_ad = host(kt.grad)
@@ -180,4 +182,4 @@ def test_fd_check_diffusion2d_512():
     worst = max(abs(a - b) / (abs(b) + gmax) for _, a, b in errs)
     log(f"fd: iterations={its} gmax={gmax:.3e} worst |fd-ad|/(|ad|+max|ad|)={worst:.2e}")
     for c, g_fd, g in errs:
-        assert abs(g_fd - g) <= 1e-5 * (abs(g) + gmax), (c, g_fd, g)
+        assert abs(g_fd - g) <= 3e-5 * (abs(g) + gmax), (c, g_fd, g)
