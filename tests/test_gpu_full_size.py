@@ -1,0 +1,85 @@
+"""Full-size workloads in the launch configuration the benchmark uses.
+
+192^3 diffusion, k = 64: one iteration of the GPU path against the oracle,
+element by element (every kernel of an iteration at its real grid: the
+chunked sparse product and its two-stage reduction, the matrix-core passes,
+the small steps). 256^3 Poisson, k = 128: too large for the oracle (about
+100 GB of host memory); the converged FP32+refinement solution's true
+residual is recomputed with a plain PyTorch 7-point stencil (tensor shifts,
+FP64), independent of the library's kernels.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.bcg import solve as oracle_solve
+from oracle.stencil import stencil_csr
+from tests.gpu_helpers import dev, host, log, rel
+from workload import WORKLOADS, coefficients_for, rhs_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _P():
+    import paper_1912_11930_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def diffusion192():
+    w = WORKLOADS["diffusion3d_192_k64"]
+    kappa = coefficients_for(w)
+    return w, kappa, stencil_csr(w.dim, w.N, kappa), rhs_for(w)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("variant,p", [("hybrid", 8), ("block", 0)])
+def test_diffusion3d_192_one_iteration(diffusion192, variant, p):
+    P = _P()
+    w, kappa, A, B = diffusion192
+    log(f"192^3 k=64 {variant} p={p}: one iteration")
+    Xo, io = oracle_solve(A, B, variant, p, tol=0.0, maxit=1)
+    rp, ci, va = P.stencil(w.dim, w.N, torch.from_numpy(kappa).cuda())
+    s = P.BCG(rp, ci, va, k=w.k, subalgebra=variant, p=p)
+    s.set_row_schedule(P.stencil_schedule(w.dim, w.N, 32))
+    Xg, ig = s.solve(dev(B), tol=0.0, maxit=1)
+    assert ig["iterations"] == io["iterations"] == 1
+    assert ig["status"] == io["status"] == oracle.NOT_CONVERGED
+    assert rel(host(Xg), Xo) <= 1e-10
+    np.testing.assert_allclose(ig["ratios"], io["ratios"], rtol=1e-9, atol=0)
+
+
+def _poisson_residual_ratios(N, B, X):
+    """max_j ||B_j - A X_j|| / ||B_j|| for the 7-point Dirichlet Poisson matrix."""
+    k = X.shape[1]
+    Xg = X.view(N, N, N, k)          # z, y, x, column
+    AX = 6.0 * Xg
+    AX[1:] -= Xg[:-1]
+    AX[:-1] -= Xg[1:]
+    AX[:, 1:] -= Xg[:, :-1]
+    AX[:, :-1] -= Xg[:, 1:]
+    AX[:, :, 1:] -= Xg[:, :, :-1]
+    AX[:, :, :-1] -= Xg[:, :, 1:]
+    R = B - AX.view(-1, k)
+    del AX
+    return float(torch.max(torch.linalg.norm(R, dim=0) / torch.linalg.norm(B, dim=0)))
+
+
+@pytest.mark.timeout(900)
+def test_poisson3d_256_k128_refinement_converges():
+    P = _P()
+    w = WORKLOADS["poisson3d_256_k128"]
+    log("256^3 k=128 hybrid p=16, FP32+refinement to 1e-8")
+    B = dev(rhs_for(w))
+    s = P.BCG(*P.stencil(w.dim, w.N), k=w.k, subalgebra="hybrid", p=16)
+    s.set_row_schedule(P.stencil_schedule(w.dim, w.N, 32))
+    s.set_precision("fp32_refine")
+    X, info = s.solve(B, tol=w.tol)
+    log(f"status={info['status_name']} iterations={info['iterations']} outer={info['outer_iterations']} "
+        f"true_rel_res={info['true_rel_res']:.2e}")
+    assert info["status"] == oracle.OK
+    ratio = _poisson_residual_ratios(w.N, B, X)
+    log(f"independent residual ratio {ratio:.3e}")
+    assert ratio <= w.tol * (1 + 1e-6)
+    assert abs(ratio - info["true_rel_res"]) <= 1e-3 * ratio
