@@ -979,6 +979,182 @@ __global__ __launch_bounds__(kBlock) void k_conv_beta_r(Plan pl, const double* _
   }
 }
 
+// ---- workgroup Gauss-Jordan for p x p groups with 16 < p <= 64 (and the
+// odd sizes below 16): [A | B] (p x 2p) in LDS; per step the pivot row and
+// column are copied aside and every thread updates its entries (thread t:
+// column t mod 2p of every (256 / 2p)-th row). Without row exchanges (line 7)
+// the pivots are the diagonals of the successive Schur complements, tested
+// with the Cholesky rule; with partial pivoting (line 12) the pivots and
+// their order are those of LU with partial pivoting.
+constexpr int kGJMaxP = 64;
+
+struct GJShared {
+  double M[kGJMaxP * 2 * kGJMaxP];
+  double colb[kGJMaxP];
+  double rowb[2 * kGJMaxP];
+  double dg0[kGJMaxP];
+  int flag[2];
+};
+
+// Returns true (workgroup-uniform) on breakdown.
+__device__ bool wg_gauss_jordan(GJShared& S, int p, bool cholesky_rule, bool pivoting) {
+  const int tid = threadIdx.x, w2 = 2 * p;
+  const int rpp = kBlock / w2;                 // rows per pass
+  const int c = tid % w2, r0 = tid / w2;      // this thread's column, first row
+  const bool act = r0 < rpp;
+  for (int j = 0; j < p; ++j) {
+    if (pivoting) {
+      if (tid < 64) {  // one wave: rows j..p-1 of column j
+        const int r = tid;
+        const bool cand = r >= j && r < p;
+        double v = cand ? fabs(S.M[r * w2 + j]) : -1.0;
+        const bool nan = __any(cand && !(v == v));
+        int key = r;
+        for (int off = 32; off > 0; off >>= 1) {
+          const double ov = __shfl_xor(v, off);
+          const int ok = __shfl_xor(key, off);
+          if (ov > v || (ov == v && ok < key)) {
+            v = ov;
+            key = ok;
+          }
+        }
+        if (tid == 0) {
+          S.flag[0] = (nan || !(v > 0.0)) ? 1 : 0;
+          S.flag[1] = key;
+        }
+      }
+      __syncthreads();
+      if (S.flag[0]) return true;
+      const int piv = S.flag[1];
+      if (piv != j) {
+        for (int cc = tid; cc < w2; cc += kBlock) {
+          const double a = S.M[j * w2 + cc];
+          S.M[j * w2 + cc] = S.M[piv * w2 + cc];
+          S.M[piv * w2 + cc] = a;
+        }
+        __syncthreads();
+      }
+    }
+    for (int cc = tid; cc < w2; cc += kBlock) S.rowb[cc] = S.M[j * w2 + cc];
+    for (int r = tid; r < p; r += kBlock) S.colb[r] = S.M[r * w2 + j];
+    __syncthreads();
+    const double d = S.rowb[j];
+    if (cholesky_rule) {
+      const double ajj = S.dg0[j];
+      if (!isfinite(d) || !(d > p * DBL_EPSILON * ajj) || !(ajj > 0.0)) return true;
+    }
+    const double inv = 1.0 / d;
+    if (act)
+      for (int r = r0; r < p; r += rpp) {
+        double* e = &S.M[r * w2 + c];
+        *e = r == j ? S.rowb[c] * inv : *e - S.colb[r] * inv * S.rowb[c];
+      }
+    __syncthreads();
+  }
+  return false;
+}
+
+// lambda_g = sym(alpha_g)^{-1} rho_g (Algorithm 1 line 7), one workgroup per group.
+__global__ __launch_bounds__(kBlock) void k_solve_lambda_gj(Plan pl, const double* __restrict__ alpha,
+                                                            const double* __restrict__ rho, double* __restrict__ lam,
+                                                            float* __restrict__ lam32, DevState* st) {
+  if (stopped(st)) return;
+  __shared__ GJShared S;
+  const int tid = threadIdx.x, g = blockIdx.x, p = pl.p, pp = p * p, w2 = 2 * p;
+  const double* al = alpha + (int64_t)g * pp;
+  const double* rh = rho + (int64_t)g * pp;
+  int bad = 0;
+  for (int e = tid; e < p * w2; e += kBlock) {
+    const int r = e / w2, c = e - r * w2;
+    const double v = c < p ? 0.5 * (al[r * p + c] + al[c * p + r]) : rh[r * p + (c - p)];
+    S.M[e] = v;
+    if (!isfinite(v)) bad = 1;
+    if (c == r) S.dg0[r] = v;
+  }
+  if (__syncthreads_or(bad) || wg_gauss_jordan(S, p, true, false)) {
+    if (tid == 0) set_status(st, BCG_EBREAKDOWN);
+    return;
+  }
+  for (int e = tid; e < pp; e += kBlock) {
+    const int r = e / p, c = e - r * p;
+    const double v = S.M[r * w2 + p + c];
+    lam[(int64_t)g * pp + e] = v;
+    lam32[(int64_t)g * pp + e] = static_cast<float>(v);
+  }
+}
+
+// Stop rule, then beta_g = rho_g^{-1} rho_new_g (Algorithm 1 lines 9-12), one
+// workgroup per group; every workgroup evaluates the rule, workgroup 0 records it.
+__global__ __launch_bounds__(kBlock) void k_conv_beta_gj(Plan pl, const double* __restrict__ red_new,
+                                                         const double* __restrict__ r0,
+                                                         const double* __restrict__ rho_old, double* __restrict__ beta,
+                                                         float* __restrict__ beta32, double* __restrict__ ratios,
+                                                         DevState* st, double tol, int it, int maxit) {
+  if (stopped(st)) return;
+  __shared__ GJShared S;
+  __shared__ double smax[kBlock];
+  __shared__ int sbad[kBlock];
+  const int tid = threadIdx.x, k = pl.k, p = pl.p, pp = p * p, w2 = 2 * p, g = blockIdx.x;
+  double m = 0.0;
+  int bad = 0;
+  for (int j = tid; j < k; j += kBlock) {
+    const double cn = red_new[pl.E + j];
+    const double rr = r0[j];
+    const double ratio = (rr == 0.0) ? 0.0 : sqrt(cn) / rr;
+    if (!isfinite(ratio))
+      bad = 1;
+    else
+      m = fmax(m, ratio);
+    if (g == 0) ratios[j] = ratio;
+  }
+  smax[tid] = m;
+  sbad[tid] = bad;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      smax[tid] = fmax(smax[tid], smax[tid + s]);
+      sbad[tid] |= sbad[tid + s];
+    }
+    __syncthreads();
+  }
+  const bool lead = g == 0 && tid == 0;
+  if (lead) {
+    st->iter = it;
+    st->max_ratio = sbad[0] ? NAN : smax[0];
+  }
+  if (sbad[0]) {
+    if (lead) set_last(st, BCG_EBREAKDOWN);
+    return;
+  }
+  if (smax[0] <= tol) {
+    if (lead) set_last(st, BCG_OK);
+    return;
+  }
+  if (it >= maxit) {
+    if (lead) set_last(st, BCG_NOT_CONVERGED);
+    return;
+  }
+  const double* ro = rho_old + (int64_t)g * pp;
+  const double* rn = red_new + (int64_t)g * pp;
+  bad = 0;
+  for (int e = tid; e < p * w2; e += kBlock) {
+    const int r = e / w2, c = e - r * w2;
+    const double v = c < p ? ro[r * p + c] : rn[r * p + (c - p)];
+    S.M[e] = v;
+    if (c < p && !isfinite(v)) bad = 1;
+  }
+  if (__syncthreads_or(bad) || wg_gauss_jordan(S, p, false, true)) {
+    if (tid == 0) set_last(st, BCG_EBREAKDOWN);
+    return;
+  }
+  for (int e = tid; e < pp; e += kBlock) {
+    const int r = e / p, c = e - r * p;
+    const double v = S.M[r * w2 + p + c];
+    beta[(int64_t)g * pp + e] = v;
+    beta32[(int64_t)g * pp + e] = static_cast<float>(v);
+  }
+}
+
 template <typename F>
 bool dispatch_small_p(int p, F&& f) {
   switch (p) {
@@ -1173,6 +1349,10 @@ void launch_solve_lambda(const Plan& pl, const double* alpha, const double* rho,
                            alpha, rho, lam, lam32, st);
       }))
     return;
+  if (pl.p > 1 && pl.p <= kGJMaxP) {
+    hipLaunchKernelGGL(k_solve_lambda_gj, dim3(pl.qo), dim3(kBlock), 0, s, pl, alpha, rho, lam, lam32, st);
+    return;
+  }
   const int grid = pl.p == 1 ? 1 : pl.qo;
   hipLaunchKernelGGL(k_solve_lambda, dim3(grid), dim3(kBlock), 0, s, pl, alpha, rho, lam, lam32, ws, st);
 }
@@ -1185,6 +1365,11 @@ void launch_conv_beta(const Plan& pl, const double* red_new, const double* r0, c
                            red_new, r0, rho_old, beta, beta32, ratios, st, tol, it, maxit);
       }))
     return;
+  if (pl.p > 1 && pl.p <= kGJMaxP) {
+    hipLaunchKernelGGL(k_conv_beta_gj, dim3(pl.qo), dim3(kBlock), 0, s, pl, red_new, r0, rho_old, beta, beta32,
+                       ratios, st, tol, it, maxit);
+    return;
+  }
   const int grid = pl.p == 1 ? 1 : pl.qo;
   hipLaunchKernelGGL(k_conv_beta, dim3(grid), dim3(kBlock), 0, s, pl, red_new, r0, rho_old, beta, beta32, ws, ratios,
                      st, tol, it, maxit);

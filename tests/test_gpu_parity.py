@@ -388,3 +388,35 @@ def test_full_size_poisson3d_128_fixed_iterations(variant, p, order):
     assert ig["iterations"] == io["iterations"] == m
     assert rel(host(Xg), Xo) <= FIXED_TOL
     np.testing.assert_allclose(ig["ratios"], io["ratios"], rtol=1e-8, atol=0)
+
+
+# ------------------------- p x p steps on workgroups (p = 3, 12, 24, 32, 64)
+@pytest.mark.parametrize("k,variant,p", [(6, "hybrid", 3), (12, "hybrid", 12), (48, "hybrid", 24), (32, "block", 0),
+                                         (64, "block", 0), (64, "global", 32)])
+def test_workgroup_small_steps(k, variant, p):
+    """Gauss-Jordan small steps for sizes outside {1, 2, 4, 8, 16}: iterates,
+    Cholesky breakdown (a group with two equal columns) and breakdown on a
+    negative definite operator, each against the oracle."""
+    log(f"workgroup small steps k={k} {variant} p={p}")
+    A = stencil_csr(2, 23, cell_coefficients(2, 23, 0.5))
+    B = rhs(A.shape[0], k, "normal", seed=500 + k)
+    Xo, io = oracle_solve(A, B, variant, p, tol=0.0, maxit=6)
+    s = _solver(A, k, variant, p)
+    Xg, ig = s.solve(dev(B), tol=0.0, maxit=6)
+    assert ig["iterations"] == io["iterations"] == 6
+    assert rel(host(Xg), Xo) <= FIXED_TOL
+    Bd = B.copy()
+    pe = k if variant == "block" else p
+    for g0 in range(0, k, pe):  # two equal columns in every group (global sums the groups)
+        Bd[:, g0 + 1] = Bd[:, g0]
+    _, od = oracle_solve(A, Bd, variant, p, tol=1e-8, maxit=50)
+    _, gd = s.solve(dev(Bd), tol=1e-8, maxit=50)
+    assert od["status"] == gd["status"] == oracle.EBREAKDOWN
+    assert od["iterations"] == gd["iterations"]
+    An = A.copy()
+    An.setdiag(-A.diagonal())
+    sn = _solver(An, k, variant, p)
+    Xn, gn = sn.solve(dev(B), tol=1e-8, maxit=50)
+    _, on = oracle_solve(An, B, variant, p, tol=1e-8, maxit=50)
+    assert gn["status"] == on["status"] == oracle.EBREAKDOWN
+    assert gn["iterations"] == on["iterations"]
