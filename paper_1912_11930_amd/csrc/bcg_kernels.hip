@@ -996,8 +996,11 @@ struct GJShared {
   int flag[2];
 };
 
-// Returns true (workgroup-uniform) on breakdown.
-__device__ bool wg_gauss_jordan(GJShared& S, int p, bool cholesky_rule, bool pivoting) {
+// Returns true (workgroup-uniform) on breakdown. NS >= the rows a thread
+// updates (p / (256 / 2p), rounded up): its entries are loaded before any is
+// stored, so the loads of a step are in flight together.
+template <int NS>
+__device__ __forceinline__ bool wg_gauss_jordan(GJShared& S, int p, bool cholesky_rule, bool pivoting) {
   const int tid = threadIdx.x, w2 = 2 * p;
   const int rpp = kBlock / w2;                 // rows per pass
   const int c = tid % w2, r0 = tid / w2;      // this thread's column, first row
@@ -1044,17 +1047,27 @@ __device__ bool wg_gauss_jordan(GJShared& S, int p, bool cholesky_rule, bool piv
       if (!isfinite(d) || !(d > p * DBL_EPSILON * ajj) || !(ajj > 0.0)) return true;
     }
     const double inv = 1.0 / d;
-    if (act)
-      for (int r = r0; r < p; r += rpp) {
-        double* e = &S.M[r * w2 + c];
-        *e = r == j ? S.rowb[c] * inv : *e - S.colb[r] * inv * S.rowb[c];
+    if (act) {
+      const double rc = S.rowb[c];
+      double t[NS];
+#pragma unroll
+      for (int u = 0; u < NS; ++u) {
+        const int r = r0 + rpp * u;
+        t[u] = r < p ? S.M[r * w2 + c] : 0.0;
       }
+#pragma unroll
+      for (int u = 0; u < NS; ++u) {
+        const int r = r0 + rpp * u;
+        if (r < p) S.M[r * w2 + c] = r == j ? rc * inv : t[u] - S.colb[r] * inv * rc;
+      }
+    }
     __syncthreads();
   }
   return false;
 }
 
 // lambda_g = sym(alpha_g)^{-1} rho_g (Algorithm 1 line 7), one workgroup per group.
+template <int NS>
 __global__ __launch_bounds__(kBlock) void k_solve_lambda_gj(Plan pl, const double* __restrict__ alpha,
                                                             const double* __restrict__ rho, double* __restrict__ lam,
                                                             float* __restrict__ lam32, DevState* st) {
@@ -1071,7 +1084,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_lambda_gj(Plan pl, const doubl
     if (!isfinite(v)) bad = 1;
     if (c == r) S.dg0[r] = v;
   }
-  if (__syncthreads_or(bad) || wg_gauss_jordan(S, p, true, false)) {
+  if (__syncthreads_or(bad) || wg_gauss_jordan<NS>(S, p, true, false)) {
     if (tid == 0) set_status(st, BCG_EBREAKDOWN);
     return;
   }
@@ -1085,6 +1098,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_lambda_gj(Plan pl, const doubl
 
 // Stop rule, then beta_g = rho_g^{-1} rho_new_g (Algorithm 1 lines 9-12), one
 // workgroup per group; every workgroup evaluates the rule, workgroup 0 records it.
+template <int NS>
 __global__ __launch_bounds__(kBlock) void k_conv_beta_gj(Plan pl, const double* __restrict__ red_new,
                                                          const double* __restrict__ r0,
                                                          const double* __restrict__ rho_old, double* __restrict__ beta,
@@ -1143,7 +1157,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_beta_gj(Plan pl, const double* 
     S.M[e] = v;
     if (c < p && !isfinite(v)) bad = 1;
   }
-  if (__syncthreads_or(bad) || wg_gauss_jordan(S, p, false, true)) {
+  if (__syncthreads_or(bad) || wg_gauss_jordan<NS>(S, p, false, true)) {
     if (tid == 0) set_last(st, BCG_EBREAKDOWN);
     return;
   }
@@ -1153,6 +1167,22 @@ __global__ __launch_bounds__(kBlock) void k_conv_beta_gj(Plan pl, const double* 
     beta[(int64_t)g * pp + e] = v;
     beta32[(int64_t)g * pp + e] = static_cast<float>(v);
   }
+}
+
+// rows per thread of the workgroup Gauss-Jordan for p, rounded up to a power of two
+template <typename F>
+void dispatch_gj_slots(int p, F&& f) {
+  const int rpp = kBlock / (2 * p), need = (p + rpp - 1) / rpp;
+  if (need <= 2)
+    f(std::integral_constant<int, 2>());
+  else if (need <= 4)
+    f(std::integral_constant<int, 4>());
+  else if (need <= 8)
+    f(std::integral_constant<int, 8>());
+  else if (need <= 16)
+    f(std::integral_constant<int, 16>());
+  else
+    f(std::integral_constant<int, 32>());
 }
 
 template <typename F>
@@ -1350,7 +1380,10 @@ void launch_solve_lambda(const Plan& pl, const double* alpha, const double* rho,
       }))
     return;
   if (pl.p > 1 && pl.p <= kGJMaxP) {
-    hipLaunchKernelGGL(k_solve_lambda_gj, dim3(pl.qo), dim3(kBlock), 0, s, pl, alpha, rho, lam, lam32, st);
+    dispatch_gj_slots(pl.p, [&](auto Nc) {
+      hipLaunchKernelGGL((k_solve_lambda_gj<decltype(Nc)::value>), dim3(pl.qo), dim3(kBlock), 0, s, pl, alpha, rho,
+                         lam, lam32, st);
+    });
     return;
   }
   const int grid = pl.p == 1 ? 1 : pl.qo;
@@ -1366,8 +1399,10 @@ void launch_conv_beta(const Plan& pl, const double* red_new, const double* r0, c
       }))
     return;
   if (pl.p > 1 && pl.p <= kGJMaxP) {
-    hipLaunchKernelGGL(k_conv_beta_gj, dim3(pl.qo), dim3(kBlock), 0, s, pl, red_new, r0, rho_old, beta, beta32,
-                       ratios, st, tol, it, maxit);
+    dispatch_gj_slots(pl.p, [&](auto Nc) {
+      hipLaunchKernelGGL((k_conv_beta_gj<decltype(Nc)::value>), dim3(pl.qo), dim3(kBlock), 0, s, pl, red_new, r0,
+                         rho_old, beta, beta32, ratios, st, tol, it, maxit);
+    });
     return;
   }
   const int grid = pl.p == 1 ? 1 : pl.qo;
