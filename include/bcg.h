@@ -122,8 +122,11 @@ int bcg_set_stream(bcg_handle *h, void *hip_stream);
 
 /*
  * bcg_set_precision -- choose FP64 or FP32 inner solves with FP64 refinement.
- *   inner_tol    relative residual reduction of each inner FP32 solve
- *                (0 < inner_tol < 1; default 1e-4).
+ *   inner_tol    depth of the inner FP32 solves: each asks for the remaining
+ *                reduction 0.5 tol / ratio, but no deeper than inner_tol / 4
+ *                (0 <= inner_tol < 1; 0 selects 4e-6 for groups of p <= 16
+ *                and 1e-4 for wider ones, where FP32 block iterates lose
+ *                accuracy sooner).
  *   inner_maxit  iteration cap of each inner solve (>= 1; default 1000).
  *   max_outer    cap on refinement steps (>= 1; default 50).
  * Not in the paper: the mixed-precision form keeps the block products, the

@@ -15,8 +15,9 @@ Outer loop:
   R = B - A X in FP64; stop when max_j ||R_j|| / ||R0_j|| <= tol;
   scale by the single scalar s = max_j ||R_j|| (a per-column scale is not an
   element of every subalgebra); solve A D = R/s in FP32 to the reduction
-  inner_target() (the remaining factor tol/ratio split evenly over the fewest
-  outer steps that each need at most inner_tol/4); X += s * D;
+  inner_target() (the remaining factor 0.5 tol/ratio, but no deeper than
+  inner_tol/4; inner_tol 0 means 4e-6 for groups of p <= 16, 1e-4 for wider
+  ones); X += s * D;
   if an outer step does not halve the largest relative residual, finish with
   the FP64 iteration from the current X (flagged in the result).
 """
@@ -91,17 +92,19 @@ def inner_solve32(A32, R32, variant, p, inner_tol, inner_maxit):
 
 def inner_target(inner_tol, tol, ratio):
     """Reduction asked of the next inner solve: the remaining factor tol/ratio
-    (with a factor 2 of margin) split evenly over the fewest outer steps that
-    each need no more than inner_tol/4."""
+    (with a factor 2 of margin), but no deeper than inner_tol/4."""
     need = 0.5 * tol / ratio
     if not (need > 0.0) or need >= 1.0:
         return inner_tol
-    floor_t = 0.25 * inner_tol
-    m = max(1.0, np.ceil(np.log(need) / np.log(floor_t) - 1e-12))
-    return float(min(max(need ** (1.0 / m), floor_t), 0.5))
+    return float(min(max(need, 0.25 * inner_tol), 0.5))
 
 
-def solve(A, B, variant="block", p=0, tol=1e-8, maxit=50, inner_tol=1e-4, inner_maxit=1000,
+def effective_inner_tol(inner_tol, p):
+    """inner_tol 0 selects 4e-6 for groups of p <= 16, 1e-4 for wider ones."""
+    return inner_tol if inner_tol > 0.0 else (4e-6 if p <= 16 else 1e-4)
+
+
+def solve(A, B, variant="block", p=0, tol=1e-8, maxit=50, inner_tol=0.0, inner_maxit=1000,
           X0=None):
     """Mixed-precision solve; returns (X, info) with FP64 X. ``maxit`` caps the
     refinement steps."""
@@ -144,7 +147,7 @@ def solve(A, B, variant="block", p=0, tol=1e-8, maxit=50, inner_tol=1e-4, inner_
             prev = ratio
             s = float(np.max(c))
             D, its, st = inner_solve32(A32, (R / s).astype(np.float32), variant, p,
-                                       inner_target(inner_tol, tol, ratio), inner_maxit)
+                                       inner_target(effective_inner_tol(inner_tol, p), tol, ratio), inner_maxit)
             info["iterations"] += its
             info["outer_iterations"] = outer
             if st < 0:

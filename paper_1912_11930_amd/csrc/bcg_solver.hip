@@ -112,7 +112,7 @@ struct bcg_handle {
   hipEvent_t ev[2] = {nullptr, nullptr};
   // refinement mode
   int precision = BCG_FP64;
-  double inner_tol = 1e-4;
+  double inner_tol = 0.0;  // 0: by group width (effective_inner_tol)
   int inner_maxit = 1000, max_outer = 50;
   float *R32 = nullptr, *P32 = nullptr, *Q32 = nullptr, *D32 = nullptr;
   int chunk = 32;       // upper bound on iterations enqueued per poll
@@ -410,17 +410,17 @@ int solve_fp64(bcg_handle* h, const double* B, double* X, double tol, int maxit,
   return fin.status;
 }
 
-// Inner reduction target of a refinement step: the remaining factor
-// tol/ratio (with a factor 2 of margin) is split evenly over the fewest outer
-// steps that each need no more than inner_tol/4, so the last step does not
-// overshoot the stop rule by a full inner tolerance.
+// Reduction asked of the next inner FP32 solve: the remaining factor
+// 0.5 tol / ratio, but no deeper than inner_tol / 4 (a deep first solve saves
+// the restart of a second one where FP32 delivers the depth).
 double inner_target(double inner_tol, double tol, double ratio) {
   const double need = 0.5 * tol / ratio;
   if (!(need > 0.0) || need >= 1.0) return inner_tol;
-  const double floor_t = 0.25 * inner_tol;
-  const double m = std::max(1.0, std::ceil(std::log(need) / std::log(floor_t) - 1e-12));
-  return std::min(std::max(std::pow(need, 1.0 / m), floor_t), 0.5);
+  return std::min(std::max(need, 0.25 * inner_tol), 0.5);
 }
+
+// inner_tol 0: 4e-6 for groups of p <= 16, 1e-4 for wider groups
+double effective_inner_tol(double inner_tol, int p) { return inner_tol > 0.0 ? inner_tol : (p <= 16 ? 4e-6 : 1e-4); }
 
 // Mixed precision: FP32 inner block CG, FP64 outer iterative refinement.
 int solve_refine(bcg_handle* h, const double* B, double* X, double tol, int maxit) {
@@ -470,7 +470,8 @@ int solve_refine(bcg_handle* h, const double* B, double* X, double tol, int maxi
         IterBuffers<float> b{h->vals32, h->D32, h->R32, h->P32, h->Q32, h->lam32, h->beta32};
         h->path = row_path(h->pl, true);
         DevState fin{};
-        if ((rc = run_iterations<float>(h, b, inner_target(h->inner_tol, tol, ratio), h->inner_maxit, &fin)))
+        const double itol = inner_target(effective_inner_tol(h->inner_tol, h->p), tol, ratio);
+        if ((rc = run_iterations<float>(h, b, itol, h->inner_maxit, &fin)))
           return rc;
         info.iterations += fin.iter;
         info.outer_iterations = outer;
@@ -610,7 +611,7 @@ int bcg_set_stream(bcg_handle* h, void* hip_stream) {
 int bcg_set_precision(bcg_handle* h, int mode, double inner_tol, int inner_maxit, int max_outer) {
   if (!h) return fail(BCG_EINVAL, "handle is NULL");
   if (mode != BCG_FP64 && mode != BCG_FP32_REFINE) return fail(BCG_EINVAL, "unknown precision mode %d", mode);
-  if (!(inner_tol > 0.0 && inner_tol < 1.0)) return fail(BCG_EINVAL, "inner_tol must be in (0, 1)");
+  if (!(inner_tol >= 0.0 && inner_tol < 1.0)) return fail(BCG_EINVAL, "inner_tol must be in [0, 1)");
   if (inner_maxit < 1 || max_outer < 1) return fail(BCG_EINVAL, "inner_maxit and max_outer must be >= 1");
   h->precision = mode;
   h->inner_tol = inner_tol;

@@ -58,7 +58,7 @@ class BCG:
         self.precision = "fp64"
 
     # -- configuration --------------------------------------------------
-    def set_precision(self, mode: str = "fp64", inner_tol: float = 1e-4, inner_maxit: int = 1000,
+    def set_precision(self, mode: str = "fp64", inner_tol: float = 0.0, inner_maxit: int = 1000,
                       max_outer: int = 50) -> None:
         if mode not in _capi.PRECISION:
             raise BCGError(_capi.BCG_EINVAL, f"unknown precision {mode!r}")
