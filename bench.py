@@ -247,19 +247,21 @@ def main() -> int:
     torch.cuda.synchronize()
 
     def run(precision: str, steps: int, warmup: int) -> dict:
-        """Warm-up solves (the last one profiles every kernel class), then
-        `steps` timed solves with events only around the dominant class."""
+        """Warm-up solves, one more solve with every kernel class profiled (the
+        breakdown; after the warm-ups, so first-launch costs stay out of it),
+        then `steps` timed solves with events only around the dominant class."""
         solver.set_precision(precision)
         X = torch.empty_like(B)
         log(f"bench: {w.name} n={n} nnz={nnz} k={k} variant={args.variant} p={p_eff} precision={precision}")
         info = None
-        for i in range(max(warmup, 1)):
-            if i == max(warmup, 1) - 1:
+        for i in range(warmup + 1):
+            profiled = i == warmup
+            if profiled:
                 solver.set_profiling(True)
             X.zero_()
             _, info = solver.solve(B, X, tol=tol, maxit=100000)
-            log(f"warmup {i}: status={info['status_name']} iterations={info['iterations']} "
-                f"{info['solve_ms']:.1f} ms true_rel_res={info['true_rel_res']:.2e}")
+            log(f"{'profiled' if profiled else 'warmup'} {i}: status={info['status_name']} "
+                f"iterations={info['iterations']} {info['solve_ms']:.1f} ms true_rel_res={info['true_rel_res']:.2e}")
         breakdown = solver.kernel_times()
         solver.set_profiling(False)
         cand = {c: breakdown[c][1] for c in ("spmm", "update_r", "update_xp")}
