@@ -198,8 +198,9 @@ enum {
   BCG_K_SPMM = 0,      /* Q = A P with the partial <<P, Q>>              */
   BCG_K_UPDATE_R = 1,  /* R -= Q lambda with <<R, R>> and column norms   */
   BCG_K_UPDATE_XP = 2, /* X += P lambda, P = R + P beta, partial <<P, R>> */
-  BCG_K_REDUCE = 3,    /* fixed-order sums of the per-workgroup partials */
-  BCG_K_SMALL = 4,     /* Cholesky / LU solves and the stop rule         */
+  BCG_K_REDUCE = 3,    /* fixed-order sums of partials outside the loop  */
+  BCG_K_SMALL = 4,     /* per-iteration sums of the partials with the
+                          Cholesky / LU solves and the stop rule they feed */
   BCG_K_RESIDUAL = 5,  /* B - A X, FP32 start of a refinement step, X += s D */
   BCG_K_PRODUCT = 6,   /* stand-alone block products (large p)           */
   BCG_NUM_KERNEL_CLASSES = 7

@@ -287,7 +287,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_fast(Plan pl, const int32_t* __
                                                       const int32_t* __restrict__ colind, const T* __restrict__ vals,
                                                       const T* __restrict__ Pm, T* __restrict__ Q,
                                                       double* __restrict__ part, const DevState* st) {
-  if (fstopped(st)) return;
+  if (halted(st)) return;
   using Gm = Geo<K, P>;
   using T2 = typename V2<T>::type;
   __shared__ T slab[4][Gm::NEED_LDS ? Gm::SLAB : 1];

@@ -19,14 +19,23 @@ constexpr int kLamLds = 2048;      // coefficient entries kept in LDS
 // Device-side solve state. Every per-iteration kernel returns at entry once
 // `done` is set. `last` marks the final iteration (stop rule met, iteration
 // cap, breakdown after the residual update): its X/P pass then applies only
-// X += P lambda, and the reduction after it sets `done`.
+// X += P lambda; the sparse product after it returns at entry and the
+// reduction after that sets `done`.
 struct DevState {
   int done;
   int status;
   int iter;
   int last;
-  double max_ratio;  // largest column ratio ||R_j|| / r0_j after the last iteration
+  unsigned int ticket;  // workgroups of a reduce-and-solve launch that have finished (0 between launches)
+  double max_ratio;     // largest column ratio ||R_j|| / r0_j after the last iteration
 };
+
+// Entry test of the sparse products: nothing is left to do once the final
+// iteration has been marked.
+__device__ __forceinline__ bool halted(const DevState* st) {
+  return st != nullptr && (*reinterpret_cast<const volatile int*>(&st->done) != 0 ||
+                           *reinterpret_cast<const volatile int*>(&st->last) != 0);
+}
 
 // Geometry of one solve: the subalgebra, the packed product layout and the
 // thread plan of the block-product accumulation.
@@ -88,12 +97,29 @@ void launch_update_xp(const Plan& pl, T* X, T* P, const T* R, const T* lam, cons
 // stand-alone product for plans whose products do not fit the fused path
 template <typename T>
 void launch_product(const Plan& pl, const T* X, const T* Y, double* part, const DevState* st, hipStream_t s);
-// finalize: the reduction after the X/P pass; on the last iteration it sets
-// `done` instead of reducing.
 // rows: partial rows to sum (-1: nwg); more than kRedSplitRows rows are
 // summed in two stages through `scratch` (kRedSplits rows of width W).
 void launch_reduce(const Plan& pl, const double* part, double* out, int width, DevState* st, hipStream_t s,
-                   int finalize = 0, int rows = -1, double* scratch = nullptr);
+                   int rows = -1, double* scratch = nullptr);
+// p x p solves of p in {2, 4, 8, 16} run in registers, one wave per group;
+// only those are fused into the reduction that produces their operands.
+bool register_solve(int p);
+// Lines 6-7: alpha = <<P, AP>> (partials of a_rows rows; more than
+// kRedSplitRows go through `scratch` first) and, for r_rows > 0, rho =
+// <<P, R>> of the previous X/P pass reduced; then lambda. A marked final
+// iteration sets `done` here instead. For register_solve(p) one launch: its
+// last workgroup to finish solves.
+void launch_reduce_lambda(const Plan& pl, const double* partA, int a_rows, double* scratch, const double* partR,
+                          int r_rows, double* alpha, double* rho, double* lam, float* lam32, double* ws, DevState* st,
+                          hipStream_t s);
+// Line 11 sums (<<R, R>> and the column norms, `rows` partial rows), then the
+// stop rule and beta (line 12); for register_solve(p) one launch whose last
+// workgroup to finish decides and solves.
+void launch_reduce_beta(const Plan& pl, const double* partN, int rows, double* red_new, const double* r0,
+                        const double* rho_old, double* beta, float* beta32, double* ws, double* ratios, DevState* st,
+                        double tol, int it, int maxit, hipStream_t s);
+// Stand-alone lambda solve, and stop rule with beta, from reduced operands:
+// workgroup Gauss-Jordan for p <= 64, LDS / global-workspace kernels beyond.
 void launch_solve_lambda(const Plan& pl, const double* alpha, const double* rho, double* lam, float* lam32,
                          double* ws, DevState* st, hipStream_t s);
 void launch_conv_beta(const Plan& pl, const double* red_new, const double* r0, const double* rho_old,

@@ -288,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_product(Plan pl, const int32_t*
                                                          const T* __restrict__ vals, const T* __restrict__ P,
                                                          T* __restrict__ Q, double* __restrict__ part,
                                                          const DevState* st) {
-  if (stopped(st)) return;
+  if (halted(st)) return;
   __shared__ T Ps[kTileElems];
   __shared__ T Qs[kTileElems];
   __shared__ double scratch[kBlock * RB * RB];
@@ -440,70 +440,87 @@ __global__ __launch_bounds__(kBlock) void k_product(Plan pl, const T* __restrict
 // Reductions and small solves
 // ------------------------------------------------------------------------
 
-// out[e] = sum over workgroups w of part[w][e], e < width, in a fixed order:
-// a block sums 16 entries, its 64 thread rows each take every 64th partial
-// (4 interleaved chains), and a fixed tree combines the 64 row sums.
+// out[e] = sum over partial rows w in [r0, r1) of part[w][e] for the EPB
+// entries e = EPB b .. EPB b + EPB - 1 below width, in a fixed order: the
+// block's 64 thread slots each take every 64th partial row (term t of slot s
+// is row r0 + s + 64 t, summed into chain t mod 4; the loads of 32 terms are
+// issued together), and a fixed tree combines the 64 slot sums. Every thread
+// of the block (64 * EPB threads) calls it.
 constexpr int kRedThreads = 1024;
+constexpr int kRedBatch = 32;
 
-__global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict__ part, double* __restrict__ out,
-                                                        int width, int W, int nwg, DevState* st, int finalize) {
-  if (stopped(st)) return;
-  if (finalize && *reinterpret_cast<const volatile int*>(&st->last)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *reinterpret_cast<volatile int*>(&st->done) = 1;
-    return;
-  }
-  __shared__ double sh[64][16];
-  const int tid = threadIdx.x, le = tid & 15, s = tid >> 4;
-  const int e = blockIdx.x * 16 + le;
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+template <int EPB>
+__device__ __forceinline__ void reduce_entries(const double* __restrict__ part, double* __restrict__ out, int width,
+                                               int W, int r0, int r1, int b, double (*sh)[EPB]) {
+  const int tid = threadIdx.x, le = tid % EPB, s = tid / EPB;
+  const int e = b * EPB + le;
+  double c[4] = {0.0, 0.0, 0.0, 0.0};
   if (e < width) {
-    int w = s;
-    for (; w + 192 < nwg; w += 256) {
-      c0 += part[(int64_t)w * W + e];
-      c1 += part[(int64_t)(w + 64) * W + e];
-      c2 += part[(int64_t)(w + 128) * W + e];
-      c3 += part[(int64_t)(w + 192) * W + e];
+    // byte offset of (row r0 + s, entry e) from the base of the batch (below
+    // 2^32: s < 64 rows of at most 65792 entries); the steps of 64 rows go
+    // into the uniform base
+    const uint32_t off = (static_cast<uint32_t>(s) * static_cast<uint32_t>(W) + static_cast<uint32_t>(e)) * 8u;
+    const size_t step = static_cast<size_t>(W) * 64 * sizeof(double);
+    for (int t0 = 0; r0 + s + 64 * t0 < r1; t0 += kRedBatch) {
+      const char* base = reinterpret_cast<const char*>(part + (int64_t)r0 * W) + step * t0;
+      double v[kRedBatch];
+#pragma unroll
+      for (int t = 0; t < kRedBatch; ++t)
+        v[t] = r0 + s + 64 * (t0 + t) < r1 ? *reinterpret_cast<const double*>(base + step * t + off) : 0.0;
+#pragma unroll
+      for (int t = 0; t < kRedBatch; ++t) c[t & 3] += v[t];
     }
-    for (; w < nwg; w += 64) c0 += part[(int64_t)w * W + e];
   }
-  sh[s][le] = (c0 + c1) + (c2 + c3);
+  sh[s][le] = (c[0] + c[1]) + (c[2] + c[3]);
   __syncthreads();
   for (int h = 32; h > 0; h >>= 1) {
     if (s < h) sh[s][le] = sh[s][le] + sh[s + h][le];
     __syncthreads();
   }
-  if (s == 0 && e < width) out[e] = sh[0][le];
+  if (s == 0 && e < width) out[e] = sh[0][le];  // wave 0 (tid < EPB) stores
 }
 
-// First stage for many partial rows: block (eb, q) sums its share of the rows
+__global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict__ part, double* __restrict__ out,
+                                                        int width, int W, int nwg, const DevState* st) {
+  if (stopped(st)) return;
+  __shared__ double sh[64][16];
+  reduce_entries<16>(part, out, width, W, 0, nwg, blockIdx.x, sh);
+}
+
+// First stage for many partial rows: block (b, q) sums its share of the rows
 // for 16 entries into row q of `out` (kRedSplits rows of stride W), in the
-// same fixed order as k_reduce; k_reduce then sums the kRedSplits rows.
+// same fixed order as k_reduce; a second pass then sums the kRedSplits rows.
 __global__ __launch_bounds__(kRedThreads) void k_reduce_rows(const double* __restrict__ part, double* __restrict__ out,
                                                              int width, int W, int rows, const DevState* st) {
   if (stopped(st)) return;
   __shared__ double sh[64][16];
-  const int tid = threadIdx.x, le = tid & 15, s = tid >> 4;
-  const int e = blockIdx.x * 16 + le, q = blockIdx.y;
+  const int q = blockIdx.y;
   const int r0 = static_cast<int>(static_cast<int64_t>(rows) * q / kRedSplits);
   const int r1 = static_cast<int>(static_cast<int64_t>(rows) * (q + 1) / kRedSplits);
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
-  if (e < width) {
-    int w = r0 + s;
-    for (; w + 192 < r1; w += 256) {
-      c0 += part[(int64_t)w * W + e];
-      c1 += part[(int64_t)(w + 64) * W + e];
-      c2 += part[(int64_t)(w + 128) * W + e];
-      c3 += part[(int64_t)(w + 192) * W + e];
+  reduce_entries<16>(part, out + (int64_t)q * W, width, W, r0, r1, blockIdx.x, sh);
+}
+
+// True in the one workgroup of the launch that finishes its share last; its
+// loads after the call see the stores of every workgroup. Wave 0 must have
+// made all of the workgroup's global stores (as reduce_entries does): its
+// release fence orders them before the ticket, so no other wave pays for a
+// fence. The last workgroup resets the ticket for the next launch. Every
+// thread calls it.
+__device__ __forceinline__ bool last_workgroup(DevState* st) {
+  __shared__ int is_last;
+  if (threadIdx.x < 64) {
+    __threadfence();  // this wave's stores before the ticket
+    if (threadIdx.x == 0) {
+      const unsigned int t = atomicAdd(&st->ticket, 1u);
+      is_last = t == gridDim.x * gridDim.y - 1;
+      if (is_last) {
+        atomicExch(&st->ticket, 0u);
+        __threadfence();  // the other workgroups' stores before the loads that follow
+      }
     }
-    for (; w < r1; w += 64) c0 += part[(int64_t)w * W + e];
   }
-  sh[s][le] = (c0 + c1) + (c2 + c3);
   __syncthreads();
-  for (int h = 32; h > 0; h >>= 1) {
-    if (s < h) sh[s][le] = sh[s][le] + sh[s + h][le];
-    __syncthreads();
-  }
-  if (s == 0 && e < width) out[(int64_t)q * W + e] = sh[0][le];
+  return is_last;
 }
 
 constexpr int kSmallLdsP = 48;  // p x p solves of up to this size run in LDS
@@ -762,78 +779,134 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
   return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
-// lambda_g = sym(alpha_g)^{-1} rho_g by Cholesky (Algorithm 1 line 7).
+// Value of lane (l - K) mod 16 within each row of 16 lanes (DPP row_ror:K).
+template <int K>
+__device__ __forceinline__ int ror16(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, 0x120 + K, 0xF, 0xF, false);
+}
+template <int K>
+__device__ __forceinline__ double ror16(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = ror16<K>(static_cast<int>(v & 0xffffffffLL));
+  const int hi = ror16<K>(static_cast<int>(v >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Maximum (NaN ignored, as by fmax) and minimum over each row of 16 lanes,
+// left in every lane of the row.
+__device__ __forceinline__ double row16_max(double v) {
+  v = fmax(v, ror16<8>(v));
+  v = fmax(v, ror16<4>(v));
+  v = fmax(v, ror16<2>(v));
+  return fmax(v, ror16<1>(v));
+}
+__device__ __forceinline__ int row16_min(int v) {
+  v = min(v, ror16<8>(v));
+  v = min(v, ror16<4>(v));
+  v = min(v, ror16<2>(v));
+  return min(v, ror16<1>(v));
+}
+
+// g itself, through a register the compiler cannot see into: keeps the
+// addresses of one group's solve from being carried across the group loop
+// (as one live pointer per access).
+__device__ __forceinline__ int opaque(int g) {
+  asm volatile("" : "+v"(g));
+  return g;
+}
+
+// 0, as an offset the compiler cannot compute before v is.
+__device__ __forceinline__ int after(double v) {
+  int z = 0;
+  asm volatile("" : "+v"(z) : "v"(v));
+  return z;
+}
+
+// 1 / sqrt(d) for finite d > 0: the hardware estimate and two Newton steps
+// (each squares the relative error), within an ulp or two.
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int n = 0; n < 2; ++n) {
+    const double e = fma(-(d * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+// lambda_g = sym(alpha_g)^{-1} rho_g by Cholesky (Algorithm 1 line 7) for
+// group g on one wave. Lane i holds row i of the symmetric part; step j takes
+// the pivot row from lane j (readlane) and every lane below updates its row
+// of the Schur complement, which stays bitwise symmetric, so row j also
+// serves as column j. Then lane c solves L L^T x = rho_:c by substitution
+// against L in LDS. Lw: P * P + P doubles of LDS owned by the wave.
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_solve_lambda_r(Plan pl, const double* __restrict__ alpha,
-                                                           const double* __restrict__ rho, double* __restrict__ lam,
-                                                           float* __restrict__ lam32, DevState* st) {
-  if (stopped(st)) return;
-  __shared__ double Ls[4][P * P];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int g = blockIdx.x * 4 + wave;
-  if (g >= pl.qo) return;
+__device__ __forceinline__ void lambda_wave(const Plan& pl, const double* alpha, const double* rho, double* lam,
+                                            float* lam32, DevState* st, int g, int lane, double* Lw) {
   constexpr int PP = P * P;
   const double* al = alpha + (int64_t)g * PP;
   const double* rh = rho + (int64_t)g * PP;
   const int i = lane < P ? lane : P - 1;
-  double a[P], L[P];
+  double a[P], y[P];
   bool bad = false;
 #pragma unroll
   for (int c = 0; c < P; ++c) {
     a[c] = 0.5 * (al[i * P + c] + al[c * P + i]);
-    L[c] = 0.0;
-    bad |= !isfinite(a[c]) || !isfinite(rh[i * P + c]);
+    y[c] = rh[c * P + i];  // column i of rho
+    bad |= !isfinite(a[c]) || !isfinite(y[c]);
   }
+  const double dg = al[i * P + i];
   bad = __any(bad);
+  double rinv = 0.0;  // 1 / L_ii
+  if (!bad) {
+    // Step j scales column j of the Schur complement by 1 / sqrt(d) (lane j:
+    // d / sqrt(d) = L_jj) and subtracts its outer product from the trailing
+    // rows. Rows <= j also run the update, on entries above the diagonal
+    // that are never read again.
 #pragma unroll
-  for (int j = 0; j < P; ++j) {
-    if (bad) break;
-    double lj[P];
+    for (int j = 0; j < P; ++j) {
+      const double d = readlane_d(a[j], j);
+      const double ajj = readlane_d(dg, j);
+      if (!isfinite(d) || !(d > P * DBL_EPSILON * ajj) || !(ajj > 0.0)) {
+        bad = true;
+        break;
+      }
+      const double r = rsqrt_nr(d);
+      a[j] *= r;
 #pragma unroll
-    for (int m = 0; m < j; ++m) lj[m] = readlane_d(L[m], j);
-    const double ajj = readlane_d(a[j], j);
-    double sacc = 0.0;
-#pragma unroll
-    for (int m = 0; m < j; ++m) sacc = fma(lj[m], lj[m], sacc);
-    const double d = ajj - sacc;
-    if (!isfinite(d) || !(d > P * DBL_EPSILON * ajj) || !(ajj > 0.0)) {
-      bad = true;
-      break;
+      for (int c = j + 1; c < P; ++c) a[c] = fma(-a[j], readlane_d(a[c], j) * r, a[c]);  // L_ij L_cj
+      rinv = lane == j ? r : rinv;
     }
-    const double ljj = sqrt(d);
-    double t = 0.0;
-#pragma unroll
-    for (int m = 0; m < j; ++m) t = fma(L[m], lj[m], t);
-    const double lij = (a[j] - t) / ljj;
-    L[j] = lane == j ? ljj : (lane > j ? lij : 0.0);
   }
   if (bad) {
     if (lane == 0) set_status(st, BCG_EBREAKDOWN);
     return;
   }
-  double* Lw = Ls[wave];
-  if (lane < P)
+  wsync();  // the wave's previous use of Lw is complete
+  if (lane < P) {
 #pragma unroll
-    for (int c = 0; c < P; ++c) Lw[lane * P + c] = L[c];
+    for (int c = 0; c < P; ++c) Lw[lane * P + c] = a[c];
+    Lw[PP + lane] = rinv;
+  }
   wsync();
   if (lane < P) {  // lane = right-hand-side column
     const int c = lane;
-    double y[P];
+    // The loads of step m are tied to the result of step m - 1 (an empty asm
+    // with that input): without it the compiler issues every load of L
+    // first and spills them.
 #pragma unroll
-    for (int r = 0; r < P; ++r) y[r] = rh[r * P + c];
+    for (int m = 0; m < P; ++m) {  // L y = rho
+      const double* Lm = Lw + after(m > 0 ? y[m - 1] : 0.0);
+      y[m] *= Lm[PP + m];
 #pragma unroll
-    for (int r = 0; r < P; ++r) {  // L y = rho
-      double t = y[r];
-#pragma unroll
-      for (int m = 0; m < r; ++m) t -= Lw[r * P + m] * y[m];
-      y[r] = t / Lw[r * P + r];
+      for (int r = m + 1; r < P; ++r) y[r] = fma(-Lm[r * P + m], y[m], y[r]);
     }
 #pragma unroll
-    for (int r = P - 1; r >= 0; --r) {  // L^T x = y
-      double t = y[r];
+    for (int m = P - 1; m >= 0; --m) {  // L^T x = y
+      const double* Lm = Lw + after(y[m < P - 1 ? m + 1 : m]);
+      y[m] *= Lm[PP + m];
 #pragma unroll
-      for (int m = r + 1; m < P; ++m) t -= Lw[m * P + r] * y[m];
-      y[r] = t / Lw[r * P + r];
+      for (int r = 0; r < m; ++r) y[r] = fma(-Lm[m * P + r], y[m], y[r]);
     }
 #pragma unroll
     for (int r = 0; r < P; ++r) {
@@ -843,19 +916,15 @@ __global__ __launch_bounds__(kBlock) void k_solve_lambda_r(Plan pl, const double
   }
 }
 
-// Stop rule (each wave decides redundantly, no workgroup barrier), then
-// beta_g = rho_g^{-1} rho_new_g by LU with partial pivoting: the largest
-// magnitude in the pivot column, the first (in the current row order) on ties.
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_conv_beta_r(Plan pl, const double* __restrict__ red_new,
-                                                        const double* __restrict__ r0,
-                                                        const double* __restrict__ rho_old, double* __restrict__ beta,
-                                                        float* __restrict__ beta32, double* __restrict__ ratios,
-                                                        DevState* st, double tol, int it, int maxit) {
-  if (stopped(st)) return;
-  __shared__ double Us[4][P * P];
-  __shared__ double Ys[4][P * P];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, k = pl.k;
+// Stop rule after the residual update (line 12): the largest column ratio
+// ||R_j|| / r0_j against tol, then the iteration cap; a non-finite ratio is
+// a breakdown. One whole wave evaluates it (every wave that calls it reaches
+// the same decision); `lead` records the state, `wr` the ratios. Returns true
+// when this iteration is the last (beta is not needed).
+__device__ __forceinline__ bool stop_rule_wave(const Plan& pl, const double* red_new, const double* __restrict__ r0,
+                                               double* __restrict__ ratios, DevState* st, double tol, int it,
+                                               int maxit, int lane, bool lead, bool wr) {
+  const int k = pl.k;
   double mx = 0.0;
   bool badr = false;
   for (int j = lane; j < k; j += 64) {
@@ -866,29 +935,40 @@ __global__ __launch_bounds__(kBlock) void k_conv_beta_r(Plan pl, const double* _
       badr = true;
     else
       mx = fmax(mx, ratio);
-    if (blockIdx.x == 0 && wave == 0) ratios[j] = ratio;
+    if (wr) ratios[j] = ratio;
   }
   for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
   badr = __any(badr);
-  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   if (lead) {
     st->iter = it;
     st->max_ratio = badr ? NAN : mx;
   }
   if (badr) {
     if (lead) set_last(st, BCG_EBREAKDOWN);
-    return;
+    return true;
   }
   if (mx <= tol) {
     if (lead) set_last(st, BCG_OK);
-    return;
+    return true;
   }
   if (it >= maxit) {
     if (lead) set_last(st, BCG_NOT_CONVERGED);
-    return;
+    return true;
   }
-  const int g = blockIdx.x * 4 + wave;
-  if (g >= pl.qo) return;
+  return false;
+}
+
+// beta_g = rho_g^{-1} rho_new_g by LU with partial pivoting (line 12) for
+// group g on one wave: the largest magnitude in the pivot column, the first
+// in the current row order on ties. Lane i holds row i of [rho | rho_new]
+// and tracks the position of that row; the pivot search runs over the 16
+// lanes of a DPP row, the pivot row is broadcast by readlane. Then lane c
+// solves U x = y_:c by back substitution against U in LDS. U: P * P + P
+// doubles (U, then its reciprocal diagonal), Yw: P * P, both owned by the wave.
+template <int P>
+__device__ __forceinline__ void beta_wave(const Plan& pl, const double* red_new, const double* rho_old, double* beta,
+                                          float* beta32, DevState* st, int g, int lane, double* U, double* Yw) {
+  static_assert(P <= 16, "one DPP row holds the candidate rows");
   constexpr int PP = P * P;
   const int i = lane < P ? lane : P - 1;
   double m[P], y[P];
@@ -900,64 +980,49 @@ __global__ __launch_bounds__(kBlock) void k_conv_beta_r(Plan pl, const double* _
     fail |= !isfinite(m[c]);
   }
   fail = __any(fail);
-  int pos = lane;  // current position of the row this lane holds
+  int pos = lane;         // current position of the row this lane holds
+  double rpiv = 0.0;      // 1 / pivot of the step that placed this row
+  if (!fail) {
 #pragma unroll
-  for (int j = 0; j < P; ++j) {
-    if (fail) break;
-    double v = (lane < P && pos >= j) ? fabs(m[j]) : -1.0;
-    int key = lane < P ? pos : 1 << 20;
-    int who = lane;
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(v, off);
-      const int ok2 = __shfl_xor(key, off);
-      const int ow = __shfl_xor(who, off);
-      if (ov > v || (ov == v && ok2 < key)) {
-        v = ov;
-        key = ok2;
-        who = ow;
+    for (int j = 0; j < P; ++j) {
+      const bool cand = lane < P && pos >= j;
+      const double v = cand ? fabs(m[j]) : -1.0;
+      const double vmax = readlane_d(row16_max(v), 0);
+      if (!(vmax > 0.0)) {
+        fail = true;
+        break;
       }
-    }
-    // lane 0's winner decides for the wave (all lanes agree unless a NaN
-    // reached the pivot column, which is a breakdown either way)
-    const double vu = readlane_d(v, 0);
-    if (!(vu > 0.0)) {
-      fail = true;
-      break;
-    }
-    const int pl_ = __builtin_amdgcn_readfirstlane(who);
-    const unsigned long long atj = __ballot(lane < P && pos == j);
-    const int la = __ffsll(static_cast<long long>(atj)) - 1;
-    const int pw = __builtin_amdgcn_readlane(pos, pl_);
-    if (lane == pl_)
-      pos = j;
-    else if (lane == la)
-      pos = pw;
-    double pr[P], py[P];
+      const int key = (cand && v == vmax) ? pos : P;
+      const int kmin = __builtin_amdgcn_readlane(row16_min(key), 0);
+      const int piv = __ffsll(static_cast<long long>(__ballot(lane < P && pos == kmin))) - 1;
+      const int at_j = __ffsll(static_cast<long long>(__ballot(lane < P && pos == j))) - 1;
+      if (lane == piv)
+        pos = j;
+      else if (lane == at_j)
+        pos = kmin;
+      const double r = 1.0 / readlane_d(m[j], piv);
+      rpiv = lane == piv ? r : rpiv;
+      // rows at or above the pivot position subtract 0 * (pivot row)
+      const double l = (lane < P && pos > j) ? m[j] * r : 0.0;
 #pragma unroll
-    for (int c = 0; c < P; ++c) {
-      pr[c] = c >= j ? readlane_d(m[c], pl_) : 0.0;
-      py[c] = readlane_d(y[c], pl_);
-    }
-    if (lane < P && pos > j) {
-      const double l = m[j] / pr[j];
+      for (int c = j + 1; c < P; ++c) m[c] = fma(-l, readlane_d(m[c], piv), m[c]);
 #pragma unroll
-      for (int c = j + 1; c < P; ++c) m[c] -= l * pr[c];
-#pragma unroll
-      for (int c = 0; c < P; ++c) y[c] -= l * py[c];
+      for (int c = 0; c < P; ++c) y[c] = fma(-l, readlane_d(y[c], piv), y[c]);
     }
   }
   if (fail) {
     if (lane == 0) set_last(st, BCG_EBREAKDOWN);
     return;
   }
-  double* U = Us[wave];
-  double* Yw = Ys[wave];
-  if (lane < P)
+  wsync();  // the wave's previous use of U and Yw is complete
+  if (lane < P) {
 #pragma unroll
     for (int c = 0; c < P; ++c) {
       U[pos * P + c] = m[c];
       Yw[pos * P + c] = y[c];
     }
+    U[PP + pos] = rpiv;
+  }
   wsync();
   if (lane < P) {
     const int c = lane;
@@ -965,11 +1030,11 @@ __global__ __launch_bounds__(kBlock) void k_conv_beta_r(Plan pl, const double* _
 #pragma unroll
     for (int r = 0; r < P; ++r) x[r] = Yw[r * P + c];
 #pragma unroll
-    for (int r = P - 1; r >= 0; --r) {
-      double t = x[r];
+    for (int mm = P - 1; mm >= 0; --mm) {  // loads tied to the previous step, as for lambda
+      const double* Um = U + after(x[mm < P - 1 ? mm + 1 : mm]);
+      x[mm] *= Um[PP + mm];
 #pragma unroll
-      for (int mm = r + 1; mm < P; ++mm) t -= U[r * P + mm] * x[mm];
-      x[r] = t / U[r * P + r];
+      for (int r = 0; r < mm; ++r) x[r] = fma(-Um[r * P + mm], x[mm], x[r]);
     }
 #pragma unroll
     for (int r = 0; r < P; ++r) {
@@ -977,6 +1042,62 @@ __global__ __launch_bounds__(kBlock) void k_conv_beta_r(Plan pl, const double* _
       beta32[(int64_t)g * PP + r * P + c] = static_cast<float>(x[r]);
     }
   }
+}
+
+// The fused reduce-and-solve launches: 8 entries per block, 512 threads
+// (the solves get the register budget of 2 waves per SIMD).
+constexpr int kFuseEntries = 8;
+constexpr int kFuseThreads = 64 * kFuseEntries;
+constexpr int kFuseWaves = kFuseThreads / 64;
+
+// Lines 6-7 in one launch: blocks [0, nb) sum alpha over a_rows partial
+// rows, blocks [nb, 2 nb) (r_rows > 0) rho over r_rows; for P > 0 the block
+// that finishes last solves for lambda, one wave per group. After the final
+// iteration it only sets `done`.
+template <int P>
+__global__ __launch_bounds__(kFuseThreads) void k_reduce_lambda(Plan pl, const double* __restrict__ partA,
+                                                                int a_rows, const double* __restrict__ partR,
+                                                                int r_rows, double* alpha, double* rho, double* lam,
+                                                                float* lam32, DevState* st) {
+  if (stopped(st)) return;
+  if (*reinterpret_cast<const volatile int*>(&st->last)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *reinterpret_cast<volatile int*>(&st->done) = 1;
+    return;
+  }
+  __shared__ double sh[64][kFuseEntries];
+  const int nb = (pl.E + kFuseEntries - 1) / kFuseEntries;
+  if (static_cast<int>(blockIdx.x) < nb)
+    reduce_entries<kFuseEntries>(partA, alpha, pl.E, pl.W, 0, a_rows, blockIdx.x, sh);
+  else
+    reduce_entries<kFuseEntries>(partR, rho, pl.E, pl.W, 0, r_rows, blockIdx.x - nb, sh);
+  if constexpr (P > 0) {
+    if (!last_workgroup(st)) return;
+    __shared__ double Ls[kFuseWaves][P * P + P];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int g = wave; g < pl.qo; g += kFuseWaves)
+      lambda_wave<P>(pl, alpha, rho, lam, lam32, st, opaque(g), lane, Ls[wave]);
+  }
+}
+
+// Line 11 sums (<<R, R>> and the column norms) over `rows` partial rows,
+// then in the block that finishes last the stop rule and beta (line 12).
+template <int P>
+__global__ __launch_bounds__(kFuseThreads) void k_reduce_beta(Plan pl, const double* __restrict__ partN, int rows,
+                                                              double* red_new, const double* __restrict__ r0,
+                                                              const double* __restrict__ rho_old,
+                                                              double* __restrict__ beta, float* __restrict__ beta32,
+                                                              double* __restrict__ ratios, DevState* st, double tol,
+                                                              int it, int maxit) {
+  if (stopped(st)) return;
+  __shared__ double sh[64][kFuseEntries];
+  reduce_entries<kFuseEntries>(partN, red_new, pl.W, pl.W, 0, rows, blockIdx.x, sh);
+  if (!last_workgroup(st)) return;
+  __shared__ double Us[kFuseWaves][P * P + P];
+  __shared__ double Ys[kFuseWaves][P * P];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (stop_rule_wave(pl, red_new, r0, ratios, st, tol, it, maxit, lane, threadIdx.x == 0, wave == 0)) return;
+  for (int g = wave; g < pl.qo; g += kFuseWaves)
+    beta_wave<P>(pl, red_new, rho_old, beta, beta32, st, opaque(g), lane, Us[wave], Ys[wave]);
 }
 
 // ---- workgroup Gauss-Jordan for p x p groups with 16 < p <= 64 (and the
@@ -1359,8 +1480,8 @@ void launch_product(const Plan& pl, const T* X, const T* Y, double* part, const 
   }
 }
 
-void launch_reduce(const Plan& pl, const double* part, double* out, int width, DevState* st, hipStream_t s,
-                   int finalize, int rows, double* scratch) {
+void launch_reduce(const Plan& pl, const double* part, double* out, int width, DevState* st, hipStream_t s, int rows,
+                   double* scratch) {
   if (rows < 0) rows = pl.nwg;
   if (rows > kRedSplitRows && scratch != nullptr) {
     hipLaunchKernelGGL(k_reduce_rows, dim3((width + 15) / 16, kRedSplits), dim3(kRedThreads), 0, s, part, scratch,
@@ -1368,17 +1489,47 @@ void launch_reduce(const Plan& pl, const double* part, double* out, int width, D
     part = scratch;
     rows = kRedSplits;
   }
-  hipLaunchKernelGGL(k_reduce, dim3((width + 15) / 16), dim3(kRedThreads), 0, s, part, out, width, pl.W, rows, st,
-                     finalize);
+  hipLaunchKernelGGL(k_reduce, dim3((width + 15) / 16), dim3(kRedThreads), 0, s, part, out, width, pl.W, rows, st);
+}
+
+bool register_solve(int p) { return p == 2 || p == 4 || p == 8 || p == 16; }
+
+void launch_reduce_lambda(const Plan& pl, const double* partA, int a_rows, double* scratch, const double* partR,
+                          int r_rows, double* alpha, double* rho, double* lam, float* lam32, double* ws, DevState* st,
+                          hipStream_t s) {
+  if (a_rows > kRedSplitRows && scratch != nullptr) {
+    hipLaunchKernelGGL(k_reduce_rows, dim3((pl.E + 15) / 16, kRedSplits), dim3(kRedThreads), 0, s, partA, scratch,
+                       pl.E, pl.W, a_rows, st);
+    partA = scratch;
+    a_rows = kRedSplits;
+  }
+  const int nb = (pl.E + kFuseEntries - 1) / kFuseEntries;
+  const dim3 grid(r_rows > 0 ? 2 * nb : nb);
+  if (dispatch_small_p(pl.p, [&](auto Pc) {
+        hipLaunchKernelGGL((k_reduce_lambda<decltype(Pc)::value>), grid, dim3(kFuseThreads), 0, s, pl, partA, a_rows,
+                           partR, r_rows, alpha, rho, lam, lam32, st);
+      }))
+    return;
+  hipLaunchKernelGGL((k_reduce_lambda<0>), grid, dim3(kFuseThreads), 0, s, pl, partA, a_rows, partR, r_rows, alpha,
+                     rho, lam, lam32, st);
+  launch_solve_lambda(pl, alpha, rho, lam, lam32, ws, st, s);
+}
+
+void launch_reduce_beta(const Plan& pl, const double* partN, int rows, double* red_new, const double* r0,
+                        const double* rho_old, double* beta, float* beta32, double* ws, double* ratios, DevState* st,
+                        double tol, int it, int maxit, hipStream_t s) {
+  if (dispatch_small_p(pl.p, [&](auto Pc) {
+        hipLaunchKernelGGL((k_reduce_beta<decltype(Pc)::value>), dim3((pl.W + kFuseEntries - 1) / kFuseEntries),
+                           dim3(kFuseThreads), 0, s, pl, partN, rows, red_new, r0, rho_old, beta, beta32, ratios, st,
+                           tol, it, maxit);
+      }))
+    return;
+  launch_reduce(pl, partN, red_new, pl.W, st, s, rows);
+  launch_conv_beta(pl, red_new, r0, rho_old, beta, beta32, ws, ratios, st, tol, it, maxit, s);
 }
 
 void launch_solve_lambda(const Plan& pl, const double* alpha, const double* rho, double* lam, float* lam32,
                          double* ws, DevState* st, hipStream_t s) {
-  if (dispatch_small_p(pl.p, [&](auto Pc) {
-        hipLaunchKernelGGL((k_solve_lambda_r<decltype(Pc)::value>), dim3((pl.qo + 3) / 4), dim3(kBlock), 0, s, pl,
-                           alpha, rho, lam, lam32, st);
-      }))
-    return;
   if (pl.p > 1 && pl.p <= kGJMaxP) {
     dispatch_gj_slots(pl.p, [&](auto Nc) {
       hipLaunchKernelGGL((k_solve_lambda_gj<decltype(Nc)::value>), dim3(pl.qo), dim3(kBlock), 0, s, pl, alpha, rho,
@@ -1393,11 +1544,6 @@ void launch_solve_lambda(const Plan& pl, const double* alpha, const double* rho,
 void launch_conv_beta(const Plan& pl, const double* red_new, const double* r0, const double* rho_old, double* beta,
                       float* beta32, double* ws, double* ratios, DevState* st, double tol, int it, int maxit,
                       hipStream_t s) {
-  if (dispatch_small_p(pl.p, [&](auto Pc) {
-        hipLaunchKernelGGL((k_conv_beta_r<decltype(Pc)::value>), dim3((pl.qo + 3) / 4), dim3(kBlock), 0, s, pl,
-                           red_new, r0, rho_old, beta, beta32, ratios, st, tol, it, maxit);
-      }))
-    return;
   if (pl.p > 1 && pl.p <= kGJMaxP) {
     dispatch_gj_slots(pl.p, [&](auto Nc) {
       hipLaunchKernelGGL((k_conv_beta_gj<decltype(Nc)::value>), dim3(pl.qo), dim3(kBlock), 0, s, pl, red_new, r0,

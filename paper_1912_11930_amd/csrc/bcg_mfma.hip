@@ -678,7 +678,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __
                                                       const int32_t* __restrict__ colind, const T* __restrict__ vals,
                                                       const T* __restrict__ Pm, T* __restrict__ Q,
                                                       double* __restrict__ part, const DevState* st) {
-  if (mstopped(st)) return;
+  if (halted(st)) return;
   using Gm = MGeo<K, PW>;
   using T2 = typename V2m<T>::type;
   constexpr int NB = Gm::NB;
@@ -857,7 +857,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma_f32(Plan pl, const int32_t
                                                           const float* __restrict__ vals, const float* __restrict__ Pm,
                                                           float* __restrict__ Q, double* __restrict__ part,
                                                           const DevState* st) {
-  if (mstopped(st)) return;
+  if (halted(st)) return;
   using Gm = MGeo<K, PW>;
   constexpr int NB = Gm::NB;
   __shared__ double smem[smem_doubles<K, PW, 0>()];

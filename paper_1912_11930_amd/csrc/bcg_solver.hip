@@ -241,9 +241,11 @@ void enqueue_iteration(bcg_handle* h, const IterBuffers<T>& b, double tol, int i
   });
   if (!fast && !pl.fused) timed(h, BCG_K_PRODUCT, it, [&] { launch_product<T>(pl, b.P, b.Q, h->partA, h->st, s); });
   const int sp_rows = mfma ? pl.sp_nwg[std::is_same<T, float>::value ? 1 : 0] : pl.nwg;
-  timed(h, BCG_K_REDUCE, it, [&] { launch_reduce(pl, h->partA, h->alpha, pl.E, h->st, s, 0, sp_rows, h->part2); });
-  timed(h, BCG_K_SMALL, it, [&] {  // line 7
-    launch_solve_lambda(pl, h->alpha, h->rho, h->lam, h->lam32, h->ws, h->st, s);
+  // line 6 (rho of the previous X/P pass; the set-up reduced the first) and
+  // line 7
+  timed(h, BCG_K_SMALL, it, [&] {
+    launch_reduce_lambda(pl, h->partA, sp_rows, h->part2, h->partR, it > 1 ? pl.nwg : 0, h->alpha, h->rho, h->lam,
+                         h->lam32, h->ws, h->st, s);
   });
   timed(h, BCG_K_UPDATE_R, it, [&] {  // line 9 and the product of line 11
     if (mfma)
@@ -254,11 +256,11 @@ void enqueue_iteration(bcg_handle* h, const IterBuffers<T>& b, double tol, int i
       launch_update_r<T>(pl, b.R, b.Q, b.lam, h->partN, h->st, s);
   });
   if (!fast && !pl.fused) timed(h, BCG_K_PRODUCT, it, [&] { launch_product<T>(pl, b.R, b.R, h->partN, h->st, s); });
-  timed(h, BCG_K_REDUCE, it, [&] { launch_reduce(pl, h->partN, h->rnew, pl.W, h->st, s); });
   timed(h, BCG_K_SMALL, it, [&] {  // stop rule, line 12
-    launch_conv_beta(pl, h->rnew, h->r0, h->rho, h->beta, h->beta32, h->ws, h->ratios, h->st, tol, it, maxit, s);
+    launch_reduce_beta(pl, h->partN, pl.nwg, h->rnew, h->r0, h->rho, h->beta, h->beta32, h->ws, h->ratios, h->st, tol,
+                       it, maxit, s);
   });
-  // line 8 and line 13 with the recomputed rho of line 6 for the next
+  // line 8 and line 13 with the partial products of line 6 for the next
   // iteration (on the last iteration only line 8)
   timed(h, BCG_K_UPDATE_XP, it, [&] {
     if (mfma)
@@ -270,7 +272,6 @@ void enqueue_iteration(bcg_handle* h, const IterBuffers<T>& b, double tol, int i
   });
   if (!fast && !pl.fused)
     timed(h, BCG_K_PRODUCT, it + 1, [&] { launch_product<T>(pl, b.P, b.R, h->partR, h->st, s); });
-  timed(h, BCG_K_REDUCE, it + 1, [&] { launch_reduce(pl, h->partR, h->rho, pl.E, h->st, s, 1); });
 }
 
 // Iterations to enqueue next: half the predicted remaining count (from the
@@ -319,7 +320,7 @@ int run_iterations(bcg_handle* h, const IterBuffers<T>& b, double tol, int maxit
     --inflight;
     const int freed = slot_head;
     slot_head ^= 1;
-    if (seen.done) break;
+    if (seen.done || seen.last) break;
     it_a = it_b;
     r_a = r_b;
     it_b = seen.iter;
@@ -406,7 +407,7 @@ int solve_fp64(bcg_handle* h, const double* B, double* X, double tol, int maxit,
   *iterations = fin.iter;
   if (fin.iter > 0)
     HIP_TRY(hipMemcpy(h->host_ratios.data(), h->ratios, sizeof(double) * h->k, hipMemcpyDeviceToHost));
-  if (!fin.done) return BCG_NOT_CONVERGED;
+  if (!fin.done && !fin.last) return BCG_NOT_CONVERGED;
   return fin.status;
 }
 

@@ -369,6 +369,37 @@ def test_row_schedule_rejects_out_of_range():
     assert rel(host(Xg), Xo) <= FIXED_TOL
 
 
+# ---------------------------------------- stop rule at the iteration cap
+@pytest.mark.parametrize("poll", [None, "1"])
+@pytest.mark.parametrize("k,variant,p", [(8, "block", 0), (8, "hybrid", 2), (8, "parallel", 1), (6, "hybrid", 3),
+                                         (12, "hybrid", 12)])
+def test_stop_on_last_allowed_iteration(monkeypatch, poll, k, variant, p):
+    """The stop rule is tested before the iteration cap (line 12 reading): a
+    solve that converges on exactly its last allowed iteration succeeds with
+    that count, one allowed iteration fewer is NOT_CONVERGED. With a status
+    poll after every iteration (BCG_POLL_EVERY=1) the host sees the final
+    iteration before any later launch runs. Register (p = 2, 8), Gauss-Jordan
+    (p = 3, 12) and parallel (p = 1) small steps; results against the oracle."""
+    if poll:
+        monkeypatch.setenv("BCG_POLL_EVERY", poll)
+    log(f"stop at cap k={k} {variant} p={p} poll={poll}")
+    A = stencil_csr(2, 23, cell_coefficients(2, 23, 0.5))
+    B = rhs(A.shape[0], k, "normal", seed=700 + k)
+    tol = 1e-8
+    s = _solver(A, k, variant, p)
+    _, free = s.solve(dev(B), tol=tol, maxit=5000)
+    assert free["status"] == oracle.OK
+    n = free["iterations"]
+    Xg, ig = s.solve(dev(B), tol=tol, maxit=n)
+    assert ig["status"] == oracle.OK and ig["iterations"] == n
+    Xo, io = oracle_solve(A, B, variant, p, tol=0.0, maxit=n)
+    assert rel(host(Xg), Xo) <= CONVERGED_TOL
+    Xc, ic = s.solve(dev(B), tol=tol, maxit=n - 1)
+    assert ic["status"] == oracle.NOT_CONVERGED and ic["iterations"] == n - 1
+    Xo1, _ = oracle_solve(A, B, variant, p, tol=0.0, maxit=n - 1)
+    assert rel(host(Xc), Xo1) <= CONVERGED_TOL
+
+
 # ------------------------------------------ full-size launch configuration
 @pytest.mark.parametrize("variant,p,order", [("block", 0, "natural"), ("block", 0, "tiled"), ("hybrid", 4, "tiled")])
 def test_full_size_poisson3d_128_fixed_iterations(variant, p, order):
