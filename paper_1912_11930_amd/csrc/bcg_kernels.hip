@@ -442,38 +442,40 @@ __global__ __launch_bounds__(kBlock) void k_product(Plan pl, const T* __restrict
 
 // out[e] = sum over partial rows w in [r0, r1) of part[w][e] for the EPB
 // entries e = EPB b .. EPB b + EPB - 1 below width, in a fixed order: the
-// block's 64 thread slots each take every 64th partial row (term t of slot s
-// is row r0 + s + 64 t, summed into chain t mod 4; the loads of 32 terms are
-// issued together), and a fixed tree combines the 64 slot sums. Every thread
-// of the block (64 * EPB threads) calls it.
+// block's SLOTS thread slots each take every SLOTS-th partial row (term t of
+// slot s is row r0 + s + SLOTS t, summed into chain t mod 4; the loads of 32
+// terms are issued together), and a fixed tree combines the slot sums.
+// Every thread of the block (SLOTS * EPB threads) calls it; wave 0 makes the
+// stores.
 constexpr int kRedThreads = 1024;
 constexpr int kRedBatch = 32;
 
-template <int EPB>
+template <int EPB, int SLOTS>
 __device__ __forceinline__ void reduce_entries(const double* __restrict__ part, double* __restrict__ out, int width,
                                                int W, int r0, int r1, int b, double (*sh)[EPB]) {
+  static_assert(EPB <= 64, "the stores come from wave 0");
   const int tid = threadIdx.x, le = tid % EPB, s = tid / EPB;
   const int e = b * EPB + le;
   double c[4] = {0.0, 0.0, 0.0, 0.0};
   if (e < width) {
     // byte offset of (row r0 + s, entry e) from the base of the batch (below
-    // 2^32: s < 64 rows of at most 65792 entries); the steps of 64 rows go
-    // into the uniform base
+    // 2^32: s < SLOTS rows of at most 65792 entries); the steps of SLOTS
+    // rows go into the uniform base
     const uint32_t off = (static_cast<uint32_t>(s) * static_cast<uint32_t>(W) + static_cast<uint32_t>(e)) * 8u;
-    const size_t step = static_cast<size_t>(W) * 64 * sizeof(double);
-    for (int t0 = 0; r0 + s + 64 * t0 < r1; t0 += kRedBatch) {
+    const size_t step = static_cast<size_t>(W) * SLOTS * sizeof(double);
+    for (int t0 = 0; r0 + s + SLOTS * t0 < r1; t0 += kRedBatch) {
       const char* base = reinterpret_cast<const char*>(part + (int64_t)r0 * W) + step * t0;
       double v[kRedBatch];
 #pragma unroll
       for (int t = 0; t < kRedBatch; ++t)
-        v[t] = r0 + s + 64 * (t0 + t) < r1 ? *reinterpret_cast<const double*>(base + step * t + off) : 0.0;
+        v[t] = r0 + s + SLOTS * (t0 + t) < r1 ? *reinterpret_cast<const double*>(base + step * t + off) : 0.0;
 #pragma unroll
       for (int t = 0; t < kRedBatch; ++t) c[t & 3] += v[t];
     }
   }
   sh[s][le] = (c[0] + c[1]) + (c[2] + c[3]);
   __syncthreads();
-  for (int h = 32; h > 0; h >>= 1) {
+  for (int h = SLOTS / 2; h > 0; h >>= 1) {
     if (s < h) sh[s][le] = sh[s][le] + sh[s + h][le];
     __syncthreads();
   }
@@ -484,7 +486,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict
                                                         int width, int W, int nwg, const DevState* st) {
   if (stopped(st)) return;
   __shared__ double sh[64][16];
-  reduce_entries<16>(part, out, width, W, 0, nwg, blockIdx.x, sh);
+  reduce_entries<16, 64>(part, out, width, W, 0, nwg, blockIdx.x, sh);
 }
 
 // First stage for many partial rows: block (b, q) sums its share of the rows
@@ -497,7 +499,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_rows(const double* __res
   const int q = blockIdx.y;
   const int r0 = static_cast<int>(static_cast<int64_t>(rows) * q / kRedSplits);
   const int r1 = static_cast<int>(static_cast<int64_t>(rows) * (q + 1) / kRedSplits);
-  reduce_entries<16>(part, out + (int64_t)q * W, width, W, r0, r1, blockIdx.x, sh);
+  reduce_entries<16, 64>(part, out + (int64_t)q * W, width, W, r0, r1, blockIdx.x, sh);
 }
 
 // True in the one workgroup of the launch that finishes its share last; its
@@ -1047,7 +1049,8 @@ __device__ __forceinline__ void beta_wave(const Plan& pl, const double* red_new,
 // The fused reduce-and-solve launches: 8 entries per block, 512 threads
 // (the solves get the register budget of 2 waves per SIMD).
 constexpr int kFuseEntries = 8;
-constexpr int kFuseThreads = 64 * kFuseEntries;
+constexpr int kFuseSlots = 64;
+constexpr int kFuseThreads = kFuseSlots * kFuseEntries;
 constexpr int kFuseWaves = kFuseThreads / 64;
 
 // Lines 6-7 in one launch: blocks [0, nb) sum alpha over a_rows partial
@@ -1064,12 +1067,12 @@ __global__ __launch_bounds__(kFuseThreads) void k_reduce_lambda(Plan pl, const d
     if (blockIdx.x == 0 && threadIdx.x == 0) *reinterpret_cast<volatile int*>(&st->done) = 1;
     return;
   }
-  __shared__ double sh[64][kFuseEntries];
+  __shared__ double sh[kFuseSlots][kFuseEntries];
   const int nb = (pl.E + kFuseEntries - 1) / kFuseEntries;
   if (static_cast<int>(blockIdx.x) < nb)
-    reduce_entries<kFuseEntries>(partA, alpha, pl.E, pl.W, 0, a_rows, blockIdx.x, sh);
+    reduce_entries<kFuseEntries, kFuseSlots>(partA, alpha, pl.E, pl.W, 0, a_rows, blockIdx.x, sh);
   else
-    reduce_entries<kFuseEntries>(partR, rho, pl.E, pl.W, 0, r_rows, blockIdx.x - nb, sh);
+    reduce_entries<kFuseEntries, kFuseSlots>(partR, rho, pl.E, pl.W, 0, r_rows, blockIdx.x - nb, sh);
   if constexpr (P > 0) {
     if (!last_workgroup(st)) return;
     __shared__ double Ls[kFuseWaves][P * P + P];
@@ -1089,8 +1092,8 @@ __global__ __launch_bounds__(kFuseThreads) void k_reduce_beta(Plan pl, const dou
                                                               double* __restrict__ ratios, DevState* st, double tol,
                                                               int it, int maxit) {
   if (stopped(st)) return;
-  __shared__ double sh[64][kFuseEntries];
-  reduce_entries<kFuseEntries>(partN, red_new, pl.W, pl.W, 0, rows, blockIdx.x, sh);
+  __shared__ double sh[kFuseSlots][kFuseEntries];
+  reduce_entries<kFuseEntries, kFuseSlots>(partN, red_new, pl.W, pl.W, 0, rows, blockIdx.x, sh);
   if (!last_workgroup(st)) return;
   __shared__ double Us[kFuseWaves][P * P + P];
   __shared__ double Ys[kFuseWaves][P * P];

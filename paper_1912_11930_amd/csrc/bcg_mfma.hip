@@ -697,10 +697,13 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __
     e = e < n ? e : n - 1;
     return sched ? static_cast<int64_t>(sched[e]) : e;
   };
+  // entry j0 + cg (clamped into the row; the value of an entry past j1 is 0,
+  // so its product adds nothing)
   auto idx_load = [&](int j0, int j1, int& c, T& v) {
     const int jj = max(min(j0 + cg, j1 - 1), 0);
     c = colind[jj];
-    v = vals[jj];
+    const T x = vals[jj];
+    v = j0 + cg < j1 ? x : T(0);
   };
   const int64_t tw = ww.stride;
   const int64_t last = ww.end > ww.first ? ww.end - 1 : ww.first;
@@ -754,11 +757,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __
       T q0 = T(0), q1 = T(0);
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const bool in = cur.j0 + u < cur.j1;
-        const T a0 = fma(cur.vs[u], xv[u].x, q0);
-        const T a1 = fma(cur.vs[u], xv[u].y, q1);
-        q0 = in ? a0 : q0;
-        q1 = in ? a1 : q1;
+        q0 = fma(cur.vs[u], xv[u].x, q0);
+        q1 = fma(cur.vs[u], xv[u].y, q1);
       }
       q[b][0] = q0;
       q[b][1] = q1;
@@ -777,11 +777,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __
           xv[u] = *reinterpret_cast<const T2*>(Pm + (int64_t)ex.cols[u] * K + c0 + 16 * b);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          const bool in = jb + u < cur.j1;
-          const T a0 = fma(ex.vs[u], xv[u].x, q[b][0]);
-          const T a1 = fma(ex.vs[u], xv[u].y, q[b][1]);
-          q[b][0] = in ? a0 : q[b][0];
-          q[b][1] = in ? a1 : q[b][1];
+          q[b][0] = fma(ex.vs[u], xv[u].x, q[b][0]);
+          q[b][1] = fma(ex.vs[u], xv[u].y, q[b][1]);
         }
       }
     }
@@ -874,12 +871,15 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma_f32(Plan pl, const int32_t
     e = e < n ? e : n - 1;
     return sched ? static_cast<int64_t>(sched[e]) : e;
   };
+  // entries j0 + cq and j0 + cq + 4 (clamped into the row; past j1 the value
+  // is 0, so the product adds nothing)
   auto idx_load = [&](int j0, int j1, int (&c)[2], float (&v)[2]) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int jj = max(min(j0 + cq + 4 * h, j1 - 1), 0);
       c[h] = colind[jj];
-      v[h] = vals[jj];
+      const float x = vals[jj];
+      v[h] = j0 + cq + 4 * h < j1 ? x : 0.f;
     }
   };
   const int64_t tw = ww.stride;
@@ -930,13 +930,9 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma_f32(Plan pl, const int32_t
       float a[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const bool in = cur.j0 + u < cur.j1;
         const float x[4] = {xv[u].x, xv[u].y, xv[u].z, xv[u].w};
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float t = fmaf(cur.vs[u], x[e], a[e]);
-          a[e] = in ? t : a[e];
-        }
+        for (int e = 0; e < 4; ++e) a[e] = fmaf(cur.vs[u], x[e], a[e]);
       }
 #pragma unroll
       for (int e = 0; e < 4; ++e) q[b][e] = a[e];
@@ -954,13 +950,9 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma_f32(Plan pl, const int32_t
           xv[u] = *reinterpret_cast<const float4*>(Pm + (int64_t)ex.cols[u] * K + c0 + 16 * b);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          const bool in = jb + u < cur.j1;
           const float x[4] = {xv[u].x, xv[u].y, xv[u].z, xv[u].w};
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const float t = fmaf(ex.vs[u], x[e], q[b][e]);
-            q[b][e] = in ? t : q[b][e];
-          }
+          for (int e = 0; e < 4; ++e) q[b][e] = fmaf(ex.vs[u], x[e], q[b][e]);
         }
       }
     }

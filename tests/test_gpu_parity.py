@@ -16,7 +16,7 @@ from oracle.bcg import solve as oracle_solve
 from oracle.grad import kappa_vjp as oracle_kappa_vjp, sampled_outer as oracle_sampled_outer
 from oracle.stencil import stencil_csr
 from tests.gpu_helpers import csr_to_dev, dev, host, log, rel
-from workload import WORKLOADS, cell_coefficients, rhs, rhs_for
+from workload import WORKLOADS, cell_coefficients, long_range_pairs, rhs, rhs_for
 
 pytestmark = pytest.mark.gpu
 
@@ -366,6 +366,44 @@ def test_row_schedule_rejects_out_of_range():
     B = rhs(A.shape[0], 8, "uniform")
     Xo, _ = oracle_solve(A, B, "block", 0, tol=0.0, maxit=5)
     Xg, _ = s.solve(dev(B), tol=0.0, maxit=5)      # still the natural order
+    assert rel(host(Xg), Xo) <= FIXED_TOL
+
+
+# ------------------------------------------- rows longer than 8 entries
+def _long_range_csr(N=40, per_row=6):
+    """2D N^2 diffusion plus symmetric couplings at random far positions
+    (about 2 per_row per row, so rows hold 8 to ~30 entries, most of them far
+    from the diagonal), the diagonal raised by the couplings' row sums
+    (diagonally dominant, SPD)."""
+    import scipy.sparse as sp
+    A = stencil_csr(2, N, cell_coefficients(2, N, 0.5))
+    n = A.shape[0]
+    i, j = long_range_pairs(n, per_row)
+    C = sp.coo_matrix((np.full(i.size, -0.05), (i, j)), shape=(n, n)).tocsr()
+    C = C + C.T
+    d = np.asarray(abs(C).sum(axis=1)).ravel()
+    return (A + C + sp.diags(d)).tocsr()
+
+
+@pytest.mark.parametrize("path", ["default", "no_mfma", "generic"])
+@pytest.mark.parametrize("k,variant,p", [(16, "block", 0), (16, "hybrid", 4), (8, "hybrid", 2), (32, "hybrid", 32)])
+def test_long_rows_fixed_iterations(monkeypatch, path, k, variant, p):
+    """General CSR: rows of 8 to ~30 entries at scattered columns, so the
+    sparse products take more than one 8-entry batch per row. FP64 iterates
+    against the oracle after 8 iterations, on every row-kernel path."""
+    if path == "no_mfma":
+        monkeypatch.setenv("BCG_NO_MFMA", "1")
+    elif path == "generic":
+        monkeypatch.setenv("BCG_GENERIC_ONLY", "1")
+    log(f"long rows k={k} {variant} p={p} {path}")
+    A = _long_range_csr()
+    nnz = np.diff(A.indptr)
+    assert nnz.max() > 16 and (nnz > 8).mean() > 0.9
+    B = rhs(A.shape[0], k, "normal", seed=300 + k)
+    Xo, io = oracle_solve(A, B, variant, p, tol=0.0, maxit=8)
+    s = _solver(A, k, variant, p)
+    Xg, ig = s.solve(dev(B), tol=0.0, maxit=8)
+    assert ig["iterations"] == io["iterations"] == 8
     assert rel(host(Xg), Xo) <= FIXED_TOL
 
 

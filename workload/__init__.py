@@ -15,7 +15,10 @@ Draw conventions (fixed so that every consumer sees the same bits):
 * loss weights W for the differentiable solve: standard normal ``(n, k)``,
   seed 2;
 * finite-difference probe indices: ``rng.choice(N**dim, count, replace=False)``,
-  seed 3.
+  seed 3;
+* long-range index pairs (test matrices with entries far from the diagonal
+  and rows longer than the stencils'): ``rng.integers(0, n, (n * per_row, 2))``,
+  pairs with equal entries dropped, seed 4.
 
 The paper's second experiment (Section 4) uses a 2D heterogeneous Poisson
 problem with a 5-point stencil and random right-hand sides; its coefficient
@@ -32,6 +35,7 @@ SEED_COEFF = 0
 SEED_RHS = 1
 SEED_LOSS_W = 2
 SEED_FD_INDEX = 3
+SEED_PAIRS = 4
 
 
 @dataclass(frozen=True)
@@ -128,6 +132,13 @@ def loss_weights(n: int, k: int, seed: int = SEED_LOSS_W) -> np.ndarray:
 def fd_indices(ncells: int, count: int, seed: int = SEED_FD_INDEX) -> np.ndarray:
     """Distinct coefficient indices probed by the finite-difference check."""
     return np.random.default_rng(seed).choice(ncells, count, replace=False)
+
+
+def long_range_pairs(n: int, per_row: int, seed: int = SEED_PAIRS) -> Tuple[np.ndarray, np.ndarray]:
+    """Random (row, column) index pairs with row != column, about per_row per row."""
+    ij = np.random.default_rng(seed).integers(0, n, (n * per_row, 2))
+    keep = ij[:, 0] != ij[:, 1]
+    return ij[keep, 0], ij[keep, 1]
 
 
 def coefficients_for(w: Workload) -> np.ndarray | None:
