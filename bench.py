@@ -53,10 +53,16 @@ TRAFFIC_SOURCES = ("bcg_mfma.hip", "bcg_fast.hip", "bcg_internal.h", "bcg_stenci
 
 
 def kernel_hash() -> str:
+    """Hash of the row-kernel sources' code: // comments and blank lines are
+    dropped (the sources hold no // inside string literals), so a comment edit
+    keeps committed counter runs current."""
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, "paper_1912_11930_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1912_11930_amd", "csrc", f), encoding="utf-8") as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

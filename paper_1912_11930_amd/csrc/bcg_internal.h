@@ -101,7 +101,7 @@ void launch_product(const Plan& pl, const T* X, const T* Y, double* part, const 
 // summed in two stages through `scratch` (kRedSplits rows of width W).
 void launch_reduce(const Plan& pl, const double* part, double* out, int width, DevState* st, hipStream_t s,
                    int rows = -1, double* scratch = nullptr);
-// p x p solves of p in {2, 4, 8, 16} run in registers, one wave per group;
+// p x p solves of p in {2, 4, 8, 16, 32} run in registers, one wave per group;
 // only those are fused into the reduction that produces their operands.
 bool register_solve(int p);
 // Lines 6-7: alpha = <<P, AP>> (partials of a_rows rows; more than

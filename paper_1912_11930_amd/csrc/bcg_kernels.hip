@@ -763,7 +763,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_beta(Plan pl, const double* __r
   }
 }
 
-// ---- one wave per p x p group (p in {2, 4, 8, 16}), rows in registers ----
+// ---- one wave per p x p group (p in {2, 4, 8, 16, 32}), rows in registers ----
 // Lane i holds row i; the pivot row of each elimination step is broadcast
 // with readlane, so the factorisations need no LDS round trips or barriers.
 constexpr int kWaveP = 16;
@@ -838,9 +838,9 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
 
 // lambda_g = sym(alpha_g)^{-1} rho_g by Cholesky (Algorithm 1 line 7) for
 // group g on one wave. Lane i holds row i of the symmetric part; step j takes
-// the pivot row from lane j (readlane) and every lane below updates its row
-// of the Schur complement, which stays bitwise symmetric, so row j also
-// serves as column j. Then lane c solves L L^T x = rho_:c by substitution
+// row j of the Schur complement from lane j (readlane) as its column j (the
+// complement stays symmetric up to rounding), and every lane subtracts
+// L_ij / L_jj times it. Then lane c solves L L^T x = rho_:c by substitution
 // against L in LDS. Lw: P * P + P doubles of LDS owned by the wave.
 template <int P>
 __device__ __forceinline__ void lambda_wave(const Plan& pl, const double* alpha, const double* rho, double* lam,
@@ -862,7 +862,7 @@ __device__ __forceinline__ void lambda_wave(const Plan& pl, const double* alpha,
   double rinv = 0.0;  // 1 / L_ii
   if (!bad) {
     // Step j scales column j of the Schur complement by 1 / sqrt(d) (lane j:
-    // d / sqrt(d) = L_jj) and subtracts its outer product from the trailing
+    // d / sqrt(d) = L_jj) and subtracts the outer product from the trailing
     // rows. Rows <= j also run the update, on entries above the diagonal
     // that are never read again.
 #pragma unroll
@@ -874,9 +874,10 @@ __device__ __forceinline__ void lambda_wave(const Plan& pl, const double* alpha,
         break;
       }
       const double r = rsqrt_nr(d);
-      a[j] *= r;
+      a[j] *= r;                    // L_ij
+      const double l2 = a[j] * r;   // L_ij / L_jj
 #pragma unroll
-      for (int c = j + 1; c < P; ++c) a[c] = fma(-a[j], readlane_d(a[c], j) * r, a[c]);  // L_ij L_cj
+      for (int c = j + 1; c < P; ++c) a[c] = fma(-l2, readlane_d(a[c], j), a[c]);  // - L_ij L_cj
       rinv = lane == j ? r : rinv;
     }
   }
@@ -962,40 +963,48 @@ __device__ __forceinline__ bool stop_rule_wave(const Plan& pl, const double* red
 
 // beta_g = rho_g^{-1} rho_new_g by LU with partial pivoting (line 12) for
 // group g on one wave: the largest magnitude in the pivot column, the first
-// in the current row order on ties. Lane i holds row i of [rho | rho_new]
-// and tracks the position of that row; the pivot search runs over the 16
-// lanes of a DPP row, the pivot row is broadcast by readlane. Then lane c
-// solves U x = y_:c by back substitution against U in LDS. U: P * P + P
-// doubles (U, then its reciprocal diagonal), Yw: P * P, both owned by the wave.
+// in the current row order on ties. Lane i holds row i of rho and tracks the
+// position of that row; the pivot search runs over the 16-lane DPP rows
+// holding candidates (two for p = 32), the pivot row is broadcast by
+// readlane, and lane i stores its multiplier of every step in LDS. Then lane
+// c takes column c of rho_new in pivot order and solves L z = y (unit lower,
+// the multipliers in the same order of operations as an elimination of
+// [rho | rho_new]) and U x = z against L and U in LDS. LDS owned by the wave:
+// U (P * P by position, then the P reciprocal pivots), Lw (P * P by
+// physical row and step), perm (P: physical row at each position).
 template <int P>
 __device__ __forceinline__ void beta_wave(const Plan& pl, const double* red_new, const double* rho_old, double* beta,
-                                          float* beta32, DevState* st, int g, int lane, double* U, double* Yw) {
-  static_assert(P <= 16, "one DPP row holds the candidate rows");
+                                          float* beta32, DevState* st, int g, int lane, double* U, double* Lw,
+                                          int* perm) {
+  static_assert(P <= 32, "two DPP rows hold the candidate rows");
   constexpr int PP = P * P;
   const int i = lane < P ? lane : P - 1;
-  double m[P], y[P];
+  double m[P];
   bool fail = false;
 #pragma unroll
   for (int c = 0; c < P; ++c) {
     m[c] = rho_old[(int64_t)g * PP + i * P + c];
-    y[c] = red_new[(int64_t)g * PP + i * P + c];
     fail |= !isfinite(m[c]);
   }
   fail = __any(fail);
-  int pos = lane;         // current position of the row this lane holds
-  double rpiv = 0.0;      // 1 / pivot of the step that placed this row
+  int pos = lane;     // current position of the row this lane holds
+  double rpiv = 0.0;  // 1 / pivot of the step that placed this row
+  wsync();            // the wave's previous use of its LDS is complete
   if (!fail) {
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       const bool cand = lane < P && pos >= j;
       const double v = cand ? fabs(m[j]) : -1.0;
-      const double vmax = readlane_d(row16_max(v), 0);
+      const double vr = row16_max(v);
+      const double vmax = P > 16 ? fmax(readlane_d(vr, 0), readlane_d(vr, 16)) : readlane_d(vr, 0);
       if (!(vmax > 0.0)) {
         fail = true;
         break;
       }
       const int key = (cand && v == vmax) ? pos : P;
-      const int kmin = __builtin_amdgcn_readlane(row16_min(key), 0);
+      const int kr = row16_min(key);
+      const int kmin = P > 16 ? min(__builtin_amdgcn_readlane(kr, 0), __builtin_amdgcn_readlane(kr, 16))
+                              : __builtin_amdgcn_readlane(kr, 0);
       const int piv = __ffsll(static_cast<long long>(__ballot(lane < P && pos == kmin))) - 1;
       const int at_j = __ffsll(static_cast<long long>(__ballot(lane < P && pos == j))) - 1;
       if (lane == piv)
@@ -1008,31 +1017,37 @@ __device__ __forceinline__ void beta_wave(const Plan& pl, const double* red_new,
       const double l = (lane < P && pos > j) ? m[j] * r : 0.0;
 #pragma unroll
       for (int c = j + 1; c < P; ++c) m[c] = fma(-l, readlane_d(m[c], piv), m[c]);
-#pragma unroll
-      for (int c = 0; c < P; ++c) y[c] = fma(-l, readlane_d(y[c], piv), y[c]);
+      if (lane < P) Lw[lane * P + j] = l;
     }
   }
   if (fail) {
     if (lane == 0) set_last(st, BCG_EBREAKDOWN);
     return;
   }
-  wsync();  // the wave's previous use of U and Yw is complete
   if (lane < P) {
 #pragma unroll
-    for (int c = 0; c < P; ++c) {
-      U[pos * P + c] = m[c];
-      Yw[pos * P + c] = y[c];
-    }
+    for (int c = 0; c < P; ++c) U[pos * P + c] = m[c];
     U[PP + pos] = rpiv;
+    perm[pos] = lane;
   }
   wsync();
   if (lane < P) {
     const int c = lane;
+    int rowq[P];
     double x[P];
 #pragma unroll
-    for (int r = 0; r < P; ++r) x[r] = Yw[r * P + c];
+    for (int q = 0; q < P; ++q) rowq[q] = perm[q];
 #pragma unroll
-    for (int mm = P - 1; mm >= 0; --mm) {  // loads tied to the previous step, as for lambda
+    for (int q = 0; q < P; ++q) x[q] = red_new[(int64_t)g * PP + rowq[q] * P + c];
+    // L z = y: the loads of step t are tied to the result of step t - 1
+#pragma unroll
+    for (int t = 0; t < P - 1; ++t) {
+      const double* Lt = Lw + t + after(t > 0 ? x[t - 1] : 0.0);
+#pragma unroll
+      for (int q = t + 1; q < P; ++q) x[q] = fma(-Lt[rowq[q] * P], x[t], x[q]);
+    }
+#pragma unroll
+    for (int mm = P - 1; mm >= 0; --mm) {  // U x = z, loads tied to the previous step
       const double* Um = U + after(x[mm < P - 1 ? mm + 1 : mm]);
       x[mm] *= Um[PP + mm];
 #pragma unroll
@@ -1052,6 +1067,12 @@ constexpr int kFuseEntries = 8;
 constexpr int kFuseSlots = 64;
 constexpr int kFuseThreads = kFuseSlots * kFuseEntries;
 constexpr int kFuseWaves = kFuseThreads / 64;
+// waves of the last workgroup that solve (one group each); p = 32 keeps the
+// LDS of its factors to two waves
+template <int P>
+constexpr int solve_waves() {
+  return P > 16 ? 2 : kFuseWaves;
+}
 
 // Lines 6-7 in one launch: blocks [0, nb) sum alpha over a_rows partial
 // rows, blocks [nb, 2 nb) (r_rows > 0) rho over r_rows; for P > 0 the block
@@ -1075,10 +1096,11 @@ __global__ __launch_bounds__(kFuseThreads) void k_reduce_lambda(Plan pl, const d
     reduce_entries<kFuseEntries, kFuseSlots>(partR, rho, pl.E, pl.W, 0, r_rows, blockIdx.x - nb, sh);
   if constexpr (P > 0) {
     if (!last_workgroup(st)) return;
-    __shared__ double Ls[kFuseWaves][P * P + P];
+    constexpr int SW = solve_waves<P>();
+    __shared__ double Ls[SW][P * P + P];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int g = wave; g < pl.qo; g += kFuseWaves)
-      lambda_wave<P>(pl, alpha, rho, lam, lam32, st, opaque(g), lane, Ls[wave]);
+    if (wave >= SW) return;
+    for (int g = wave; g < pl.qo; g += SW) lambda_wave<P>(pl, alpha, rho, lam, lam32, st, opaque(g), lane, Ls[wave]);
   }
 }
 
@@ -1095,12 +1117,15 @@ __global__ __launch_bounds__(kFuseThreads) void k_reduce_beta(Plan pl, const dou
   __shared__ double sh[kFuseSlots][kFuseEntries];
   reduce_entries<kFuseEntries, kFuseSlots>(partN, red_new, pl.W, pl.W, 0, rows, blockIdx.x, sh);
   if (!last_workgroup(st)) return;
-  __shared__ double Us[kFuseWaves][P * P + P];
-  __shared__ double Ys[kFuseWaves][P * P];
+  constexpr int SW = solve_waves<P>();
+  __shared__ double Us[SW][P * P + P];
+  __shared__ double Ls[SW][P * P];
+  __shared__ int Pm[SW][P];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (wave >= SW) return;
   if (stop_rule_wave(pl, red_new, r0, ratios, st, tol, it, maxit, lane, threadIdx.x == 0, wave == 0)) return;
-  for (int g = wave; g < pl.qo; g += kFuseWaves)
-    beta_wave<P>(pl, red_new, rho_old, beta, beta32, st, opaque(g), lane, Us[wave], Ys[wave]);
+  for (int g = wave; g < pl.qo; g += SW)
+    beta_wave<P>(pl, red_new, rho_old, beta, beta32, st, opaque(g), lane, Us[wave], Ls[wave], Pm[wave]);
 }
 
 // ---- workgroup Gauss-Jordan for p x p groups with 16 < p <= 64 (and the
@@ -1316,6 +1341,7 @@ bool dispatch_small_p(int p, F&& f) {
     case 4: f(std::integral_constant<int, 4>()); return true;
     case 8: f(std::integral_constant<int, 8>()); return true;
     case 16: f(std::integral_constant<int, 16>()); return true;
+    case 32: f(std::integral_constant<int, 32>()); return true;
     default: return false;
   }
 }
@@ -1495,7 +1521,7 @@ void launch_reduce(const Plan& pl, const double* part, double* out, int width, D
   hipLaunchKernelGGL(k_reduce, dim3((width + 15) / 16), dim3(kRedThreads), 0, s, part, out, width, pl.W, rows, st);
 }
 
-bool register_solve(int p) { return p == 2 || p == 4 || p == 8 || p == 16; }
+bool register_solve(int p) { return p == 2 || p == 4 || p == 8 || p == 16 || p == 32; }
 
 void launch_reduce_lambda(const Plan& pl, const double* partA, int a_rows, double* scratch, const double* partR,
                           int r_rows, double* alpha, double* rho, double* lam, float* lam32, double* ws, DevState* st,

@@ -459,11 +459,12 @@ def test_full_size_poisson3d_128_fixed_iterations(variant, p, order):
     np.testing.assert_allclose(ig["ratios"], io["ratios"], rtol=1e-8, atol=0)
 
 
-# ------------------------- p x p steps on workgroups (p = 3, 12, 24, 32, 64)
+# -------- p x p steps on workgroups (p = 3, 12, 24, 64) and in registers (p = 32)
 @pytest.mark.parametrize("k,variant,p", [(6, "hybrid", 3), (12, "hybrid", 12), (48, "hybrid", 24), (32, "block", 0),
                                          (64, "block", 0), (64, "global", 32)])
 def test_workgroup_small_steps(k, variant, p):
-    """Gauss-Jordan small steps for sizes outside {1, 2, 4, 8, 16}: iterates,
+    """Gauss-Jordan small steps for sizes outside {1, 2, 4, 8, 16, 32}, and the
+    register steps at p = 32 (two 16-lane pivot rows): iterates,
     Cholesky breakdown (a group with two equal columns) and breakdown on a
     negative definite operator, each against the oracle."""
     log(f"workgroup small steps k={k} {variant} p={p}")
