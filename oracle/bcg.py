@@ -25,6 +25,12 @@ k, q = k/p column groups. Readings of the text that the paper leaves open:
 * a zero initial-residual column is invalid input unless the subalgebra is
   the diagonal one (parallel, or hybrid with p = 1), where that column's lane
   gets lambda = beta = 0 (1x1 system 0*lambda = 0).
+
+With ``precond="jacobi"`` the preconditioner of Algorithm 1 is M = diag(A)
+(lines 2, 10, 11 and 13 use Z = M^{-1} R); reading: the stop rule then
+measures each column in the M^{-1}-norm, sqrt(R_j^T M^{-1} R_j), relative to
+its initial value (the residual norm preconditioned CG carries), and a
+diagonal that is not positive and finite is invalid input.
 """
 from __future__ import annotations
 
@@ -173,20 +179,32 @@ def solve_beta(rho_old: np.ndarray, rho_new: np.ndarray, decoupled: bool) -> np.
     return out
 
 
-def column_norms(R: np.ndarray) -> np.ndarray:
-    return np.sqrt(np.einsum("ij,ij->j", R, R))
+def apply_diag_inverse(V: np.ndarray, minv: np.ndarray | None) -> np.ndarray:
+    """M^{-1} V for a diagonal preconditioner given by M^{-1} (one value per
+    row); V itself for M = I."""
+    return V if minv is None else V * minv[:, None]
+
+
+def column_norms(R: np.ndarray, minv: np.ndarray | None = None) -> np.ndarray:
+    """Euclidean column norms, or the M^{-1}-norms sqrt(R_j^T M^{-1} R_j) for a
+    diagonal M given by its inverse ``minv`` (one value per row)."""
+    if minv is None:
+        return np.sqrt(np.einsum("ij,ij->j", R, R))
+    return np.sqrt(np.einsum("ij,ij,i->j", R, R, minv))
 
 
 def solve(A, B: np.ndarray, variant: str = "block", p: int = 0, tol: float = 1e-8,
           maxit: int = 1000, X0: np.ndarray | None = None, ref_norms: np.ndarray | None = None,
-          callback=None):
-    """Run Algorithm 1 (M = I) and return (X, info).
+          callback=None, precond: str = "none"):
+    """Run Algorithm 1 (M = I, or M = diag(A) with precond="jacobi") and
+    return (X, info).
 
     info: status, iterations, r0 (reference column norms), ratios (final
-    ||R_j|| / r0_j of the recursive residual). tol = 0 runs exactly ``maxit``
-    iterations (fixed-iteration mode). ``ref_norms`` replaces the initial
-    residual norms in the stop rule (used by the refinement fallback).
-    ``callback(i, X, R)`` is called after each iteration's line 9.
+    ||R_j|| / r0_j of the recursive residual, M^{-1}-norms with Jacobi).
+    tol = 0 runs exactly ``maxit`` iterations (fixed-iteration mode).
+    ``ref_norms`` replaces the initial residual norms in the stop rule (used
+    by the refinement fallback). ``callback(i, X, R)`` is called after each
+    iteration's line 9.
     """
     B = np.asarray(B, dtype=np.float64)
     n, k = B.shape
@@ -201,12 +219,25 @@ def solve(A, B: np.ndarray, variant: str = "block", p: int = 0, tol: float = 1e-
         info["status"] = EINVAL
         return X, info
     dec = decoupled_columns(variant, p)
+    if precond not in ("none", "jacobi"):
+        info["status"] = EINVAL
+        return X, info
+    minv = None  # M^{-1} as one value per row (M = diag(A))
+    if precond == "jacobi":
+        d = np.asarray(A.diagonal(), dtype=np.float64)
+        if not np.all(np.isfinite(d) & (d > 0.0)):
+            info["status"] = EINVAL
+            return X, info
+        minv = 1.0 / d
 
-    # line 1: R^0 = B - A X^0 ; line 2: P^1 = M^{-1} R^0 = R^0
+    def apply_minv(V):
+        return apply_diag_inverse(V, minv)
+
+    # line 1: R^0 = B - A X^0 ; line 2: P^1 = M^{-1} R^0
     R = B - A @ X
-    r0 = column_norms(R) if ref_norms is None else np.asarray(ref_norms, dtype=np.float64)
+    r0 = column_norms(R, minv) if ref_norms is None else np.asarray(ref_norms, dtype=np.float64)
     info["r0"] = r0
-    if not np.all(np.isfinite(column_norms(R))):
+    if not np.all(np.isfinite(column_norms(R, minv))):
         info["status"] = EINVAL
         return X, info
     if np.all(r0 == 0.0):
@@ -216,8 +247,8 @@ def solve(A, B: np.ndarray, variant: str = "block", p: int = 0, tol: float = 1e-
         info["status"] = EINVAL
         return X, info
     safe_r0 = np.where(r0 == 0.0, 1.0, r0)
-    P = R.copy()
-    ratios = column_norms(R) / safe_r0
+    P = apply_minv(R).copy()
+    ratios = column_norms(R, minv) / safe_r0
     for i in range(1, maxit + 1):
         Q = A @ P                                        # line 4
         alpha = block_product(P, Q, variant, p)          # line 5
@@ -230,7 +261,7 @@ def solve(A, B: np.ndarray, variant: str = "block", p: int = 0, tol: float = 1e-
         X = X + apply_coeff(P, lam, p)                   # line 8
         R = R - apply_coeff(Q, lam, p)                   # line 9
         info["iterations"] = i
-        ratios = np.where(r0 == 0.0, 0.0, column_norms(R) / safe_r0)
+        ratios = np.where(r0 == 0.0, 0.0, column_norms(R, minv) / safe_r0)
         if callback is not None:
             callback(i, X, R)
         if np.max(ratios) <= tol:
@@ -239,12 +270,13 @@ def solve(A, B: np.ndarray, variant: str = "block", p: int = 0, tol: float = 1e-
         if not np.all(np.isfinite(ratios)):
             info.update(status=EBREAKDOWN, ratios=ratios)
             return X, info
-        rho_new = block_product(R, R, variant, p)        # lines 10-11 (Z = R)
+        Z = apply_minv(R)                                # line 10
+        rho_new = block_product(Z, R, variant, p)        # line 11
         try:
             beta = solve_beta(rho_old, rho_new, dec)     # line 12
         except Breakdown:
             info.update(status=EBREAKDOWN, ratios=ratios)
             return X, info
-        P = R + apply_coeff(P, beta, p)                  # line 13, sign read as '+'
+        P = Z + apply_coeff(P, beta, p)                  # line 13, sign read as '+'
     info.update(status=NOT_CONVERGED, ratios=ratios)
     return X, info

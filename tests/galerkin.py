@@ -39,17 +39,21 @@ def subalgebra_basis(variant: str, k: int, p: int):
     return basis
 
 
-def galerkin_iterate(A, B, X0, variant, p, m):
+def galerkin_iterate(A, B, X0, variant, p, m, minv=None):
+    """m-th iterate; with a diagonal preconditioner (``minv`` = M^{-1}, one
+    value per row) the space is X0 + K^m_S(M^{-1} A, M^{-1} R0), the one the
+    preconditioned iteration searches, with the same A-norm criterion."""
     A = np.asarray(A.todense()) if hasattr(A, "todense") else np.asarray(A)
     R0 = B - A @ X0
     k = B.shape[1]
     basis = subalgebra_basis(variant, k, p)
+    scale = (lambda V: V) if minv is None else (lambda V: V * np.asarray(minv)[:, None])
     dirs = []
-    V = R0
+    V = scale(R0)
     for _ in range(m):
         for E in basis:
             dirs.append(V @ E)
-        V = A @ V
+        V = scale(A @ V)
     nd = len(dirs)
     G = np.empty((nd, nd))
     h = np.empty(nd)

@@ -91,3 +91,32 @@ def test_minus_sign_update_is_caught(monkeypatch):
     X, _ = ob.solve(A, B[:, :1], "block", 0, tol=0.0, maxit=3)
     assert np.linalg.norm(X[:, 0] - x2) > 1e-6 * np.linalg.norm(x2)
     assert _galerkin_mismatch("block", 4) > 1e-6
+
+
+_orig_minv = ob.apply_diag_inverse
+
+
+@pytest.mark.parametrize("mutation", ["preconditioner_dropped", "m_instead_of_m_inverse"])
+@pytest.mark.parametrize("variant,p", [("block", 4), ("hybrid", 2), ("global", 2)])
+def test_jacobi_mutation_is_caught(monkeypatch, mutation, variant, p):
+    # Lines 2 and 10 of the preconditioned iteration: Z = R (M ignored) or
+    # Z = M R (inverse forgotten) must fail the preconditioned Galerkin pin.
+    if mutation == "preconditioner_dropped":
+        monkeypatch.setattr(ob, "apply_diag_inverse", lambda V, minv: V)
+    else:
+        monkeypatch.setattr(ob, "apply_diag_inverse",
+                            lambda V, minv: V if minv is None else V / minv[:, None])
+    A, B, X0 = _setup()
+    minv = 1.0 / A.diagonal()
+    X, _ = ob.solve(A, B, variant, p, tol=0.0, maxit=3, X0=X0, precond="jacobi")
+    Xg = galerkin_iterate(A, B, X0, variant, p, 3, minv=minv)
+    assert np.linalg.norm(X - Xg) > 1e-6 * np.linalg.norm(Xg)
+
+
+def test_jacobi_unmutated_passes():
+    A, B, X0 = _setup()
+    minv = 1.0 / A.diagonal()
+    for v, p in [("block", 4), ("hybrid", 2), ("global", 2)]:
+        X, _ = ob.solve(A, B, v, p, tol=0.0, maxit=3, X0=X0, precond="jacobi")
+        Xg = galerkin_iterate(A, B, X0, v, p, 3, minv=minv)
+        assert np.linalg.norm(X - Xg) < 1e-9 * np.linalg.norm(Xg)
