@@ -164,7 +164,7 @@ def traffic_from(directory: str, workload: str, variant: str) -> int:
     return 0
 
 
-def cpu_baseline(w, variant: str, p: int, gpu_iterations: int, budget_s: float):
+def cpu_baseline(w, variant: str, p: int, gpu_iterations: int, budget_s: float, precond: str = "none"):
     """Time the oracle's iterations on the full system; scale to the solve."""
     import numpy as np
     from threadpoolctl import threadpool_info
@@ -177,11 +177,11 @@ def cpu_baseline(w, variant: str, p: int, gpu_iterations: int, budget_s: float):
     B = rhs_for(w)
     # one iteration to calibrate, then as many as fit the budget
     t0 = time.perf_counter()
-    oracle_solve(A, B, variant, p, tol=0.0, maxit=1)
+    oracle_solve(A, B, variant, p, tol=0.0, maxit=1, precond=precond)
     t1 = time.perf_counter() - t0
     m = max(2, min(gpu_iterations, int(budget_s / max(t1, 1e-3))))
     t0 = time.perf_counter()
-    _, info = oracle_solve(A, B, variant, p, tol=0.0, maxit=m)
+    _, info = oracle_solve(A, B, variant, p, tol=0.0, maxit=m, precond=precond)
     tm = time.perf_counter() - t0
     per_it = tm / m
     t_solve = per_it * gpu_iterations
@@ -192,7 +192,8 @@ def cpu_baseline(w, variant: str, p: int, gpu_iterations: int, budget_s: float):
         "unit": "RHS-solves/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": (f"{m} iterations of the FP64 NumPy/SciPy oracle ({variant}, p={p}) on the full "
+        "sample": (f"{m} iterations of the FP64 NumPy/SciPy oracle ({variant}, p={p}"
+                   f"{', Jacobi' if precond != 'none' else ''}) on the full "
                    f"{w.name} system ({tm:.1f} s, {per_it * 1e3:.0f} ms/iteration), scaled to the GPU's "
                    f"{gpu_iterations} iterations; sparse product single-threaded, BLAS on {cores} threads, "
                    f"host has {os.cpu_count()} logical CPUs"),
@@ -213,6 +214,8 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precond", default="none", choices=["none", "jacobi"],
+                    help="preconditioner M of Algorithm 1 (jacobi: M = diag(A))")
     ap.add_argument("--schedule", default="tiled", choices=["tiled", "natural"],
                     help="row order of the sparse product: 32x32 x-y tiles swept through z (3D), or natural")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -245,6 +248,8 @@ def main() -> int:
     B = torch.from_numpy(rhs_for(w)).to(dev)
     n, k, nnz = w.n, w.k, w.nnz
     solver = P.BCG(rp, ci, va, k=k, subalgebra=args.variant, p=args.p)
+    if args.precond != "none":
+        solver.set_preconditioner(args.precond)
     schedule = "natural"
     if args.schedule == "tiled" and w.dim == 3:
         solver.set_row_schedule(P.stencil_schedule(w.dim, w.N, 32, device=dev))
@@ -322,7 +327,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": w.name, "grid": f"{w.N}^{w.dim}", "n": n, "nnz": nnz, "k": k,
                    "variant": args.variant, "p": p_eff, "precision": args.precision, "tol": tol,
-                   "rhs": w.rhs, "row_schedule": schedule},
+                   "rhs": w.rhs, "row_schedule": schedule, "precond": args.precond},
         "iterations": head["iterations"],
         "outer_iterations": info["outer_iterations"] if info else None,
         "true_rel_res": info["true_rel_res"] if info else None,
@@ -350,7 +355,8 @@ def main() -> int:
         }
     if not args.no_cpu_baseline:
         log("cpu_baseline: timing the oracle ...")
-        out["cpu_baseline"] = cpu_baseline(w, args.variant, p_eff, head_fp64_iterations(out), args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(w, args.variant, p_eff, head_fp64_iterations(out), args.cpu_budget,
+                                           args.precond)
     print(json.dumps(out), flush=True)
     return 0
 

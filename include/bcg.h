@@ -155,8 +155,29 @@ int bcg_set_precision(bcg_handle *h, int mode, double inner_tol, int inner_maxit
 int bcg_solve(bcg_handle *h, const double *B, double *X, double tol, int maxit);
 
 /* Copies new matrix values (same pattern as at create; device array of nnz
- * FP64) into the handle, e.g. for a differentiable solve. Stream-ordered. */
+ * FP64) into the handle, e.g. for a differentiable solve. Stream-ordered;
+ * with the Jacobi preconditioner on, also recomputes its scaling and waits
+ * for it (BCG_EINVAL, and the preconditioner off, if the new diagonal is
+ * not positive). */
 int bcg_update_values(bcg_handle *h, const double *values);
+
+/*
+ * bcg_set_preconditioner -- the preconditioner M of Algorithm 1 (lines 2,
+ * 10, 11 and 13). kind: BCG_PRECOND_NONE (M = I, the default) or
+ * BCG_PRECOND_JACOBI (M = diag(A)). Jacobi runs block CG on the
+ * symmetrically scaled system D^{-1/2} A D^{-1/2} Y = D^{-1/2} B, X =
+ * D^{-1/2} Y, whose iterates are those of Algorithm 1 with M = diag(A); the
+ * stop rule then compares the M^{-1}-norms sqrt(R_j^T M^{-1} R_j) of the
+ * recursive residual columns with their initial values (info.max_rel_res,
+ * bcg_get_column_ratios), while info.true_rel_res stays the Euclidean
+ * ||B - A X||_j / ||B - A X0||_j. Needs a positive finite diagonal entry in
+ * every row: BCG_EINVAL otherwise (preconditioner left off). The handle
+ * keeps n scale factors and scaled FP64 and FP32 copies of the values, and
+ * from the first solve on an n x k FP64 block for the scaled B; B itself is
+ * not modified, X is scaled in place during the solve. Synchronous.
+ */
+enum { BCG_PRECOND_NONE = 0, BCG_PRECOND_JACOBI = 1 };
+int bcg_set_preconditioner(bcg_handle *h, int kind);
 
 /*
  * bcg_csr_outer -- sampled outer product on the pattern of A:

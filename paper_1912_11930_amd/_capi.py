@@ -20,6 +20,7 @@ BCG_EHIP = -4
 
 SUBALGEBRA = {"block": 0, "global": 1, "parallel": 2, "hybrid": 3}
 PRECISION = {"fp64": 0, "fp32_refine": 1}
+PRECOND = {"none": 0, "jacobi": 1}
 STATUS_NAME = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EBREAKDOWN", -3: "ENOMEM", -4: "EHIP"}
 
 
@@ -55,6 +56,7 @@ SIGNATURES = [
     ("bcg_solve", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                  ctypes.c_int]),
     ("bcg_update_values", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("bcg_set_preconditioner", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("bcg_csr_outer", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                      ctypes.c_void_p]),
     ("bcg_get_info", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),

@@ -23,6 +23,7 @@
 
 #include "../../include/bcg.h"
 #include "bcg_internal.h"
+#include "bcg_scale.h"
 
 namespace bcg {
 
@@ -1406,7 +1407,78 @@ __global__ __launch_bounds__(kBlock) void k_check_range(const int32_t* __restric
   }
 }
 
+// Jacobi preconditioner M = diag(A): s_i = 1 / sqrt(a_ii) (duplicate
+// diagonal entries summed). flag = 1 when a row has no diagonal entry or
+// a_ii is not positive and finite (s_i = 1 there).
+__global__ __launch_bounds__(kBlock) void k_jacobi_scale(int64_t n, const int32_t* __restrict__ rowptr,
+                                                         const int32_t* __restrict__ colind,
+                                                         const double* __restrict__ vals, double* __restrict__ dscale,
+                                                         int* __restrict__ flag) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    double d = 0.0;
+    bool found = false;
+    const int j1 = rowptr[i + 1];
+    for (int j = rowptr[i]; j < j1; ++j)
+      if (colind[j] == i) {
+        d += vals[j];
+        found = true;
+      }
+    const bool ok = found && d > 0.0 && isfinite(d);
+    if (!ok) *reinterpret_cast<volatile int*>(flag) = 1;
+    dscale[i] = ok ? 1.0 / sqrt(d) : 1.0;
+  }
+}
+
+// Values of D^{-1/2} A D^{-1/2}: s_row * a * s_col, in FP64 and FP32.
+__global__ __launch_bounds__(kBlock) void k_scale_values(int64_t n, const int32_t* __restrict__ rowptr,
+                                                         const int32_t* __restrict__ colind,
+                                                         const double* __restrict__ vals,
+                                                         const double* __restrict__ dscale, double* __restrict__ vs,
+                                                         float* __restrict__ vs32) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    const double si = dscale[i];
+    const int j1 = rowptr[i + 1];
+    for (int j = rowptr[i]; j < j1; ++j) {
+      const double v = si * vals[j] * dscale[colind[j]];
+      vs[j] = v;
+      vs32[j] = static_cast<float>(v);
+    }
+  }
+}
+
+// dst = D^{-1/2} src (divide = 0) or D^{1/2} src (divide = 1), row-major
+// n x k; dst may be src.
+__global__ __launch_bounds__(kBlock) void k_scale_rows(int64_t n, int k, const double* src,
+                                                       const double* __restrict__ dscale, double* dst, int divide) {
+  const int64_t count = n * k;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < count; e += (int64_t)gridDim.x * kBlock) {
+    const double si = dscale[e / k];
+    dst[e] = divide ? src[e] / si : src[e] * si;
+  }
+}
+
 }  // namespace
+
+void launch_jacobi_scale(int64_t n, const int32_t* rowptr, const int32_t* colind, const double* vals, double* dscale,
+                         int* flag, hipStream_t s) {
+  const int64_t blocks = (n + kBlock - 1) / kBlock;
+  const int grid = static_cast<int>(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096);
+  hipLaunchKernelGGL(k_jacobi_scale, dim3(grid), dim3(kBlock), 0, s, n, rowptr, colind, vals, dscale, flag);
+}
+
+void launch_scale_values(int64_t n, const int32_t* rowptr, const int32_t* colind, const double* vals,
+                         const double* dscale, double* vs, float* vs32, hipStream_t s) {
+  const int64_t blocks = (n + kBlock - 1) / kBlock;
+  const int grid = static_cast<int>(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096);
+  hipLaunchKernelGGL(k_scale_values, dim3(grid), dim3(kBlock), 0, s, n, rowptr, colind, vals, dscale, vs, vs32);
+}
+
+void launch_scale_rows(int64_t n, int k, const double* src, const double* dscale, double* dst, int divide,
+                       hipStream_t s) {
+  const int64_t blocks = (n * k + kBlock - 1) / kBlock;
+  const int grid = static_cast<int>(blocks < 8192 ? (blocks > 0 ? blocks : 1) : 8192);
+  hipLaunchKernelGGL(k_scale_rows, dim3(grid), dim3(kBlock), 0, s, n, k, src, dscale, dst, divide);
+}
 
 void launch_check_range(const int32_t* order, int64_t n, int* flag, hipStream_t s) {
   const int64_t blocks = (n + kBlock - 1) / kBlock;

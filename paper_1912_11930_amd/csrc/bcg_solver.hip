@@ -21,6 +21,7 @@
 
 #include "../../include/bcg.h"
 #include "bcg_internal.h"
+#include "bcg_scale.h"
 
 using namespace bcg;
 
@@ -130,6 +131,13 @@ struct bcg_handle {
   std::vector<double> ref_r0;  // host copy of the stop rule's reference norms
   bcg_info info{};
   std::vector<double> host_ratios;
+  // Jacobi preconditioning by symmetric scaling
+  int precond = BCG_PRECOND_NONE;
+  double* dscale = nullptr;   // diag(A)^{-1/2}
+  double* vals_s = nullptr;   // values of D^{-1/2} A D^{-1/2}
+  float* vals32_s = nullptr;
+  double* Bs = nullptr;       // D^{-1/2} B of the current solve
+  std::vector<double> true_r0;  // ||B - A X0||_j of the current solve
 };
 
 namespace {
@@ -137,7 +145,8 @@ namespace {
 void free_all(bcg_handle* h) {
   void* ptrs[] = {h->rowptr, h->colind, h->vals, h->vals32, h->R, h->P, h->Q, h->partA, h->part2, h->partR, h->partN,
                   h->alpha, h->rho, h->rnew, h->lam, h->beta, h->ws, h->lam32, h->beta32, h->r0, h->ratios,
-                  h->scale, h->st, h->R32, h->P32, h->Q32, h->D32, h->sched};
+                  h->scale, h->st, h->R32, h->P32, h->Q32, h->D32, h->sched, h->dscale, h->vals_s,
+                  h->vals32_s, h->Bs};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->st_host) (void)hipHostFree(h->st_host);
@@ -499,6 +508,26 @@ int solve_refine(bcg_handle* h, const double* B, double* X, double tol, int maxi
   }
 }
 
+// Scale factors and scaled values of the Jacobi preconditioner for the
+// handle's current values. Synchronous (reads the flag).
+int jacobi_prepare(bcg_handle* h) {
+  int rc;
+  const int64_t nz = h->nnz > 0 ? h->nnz : 1;
+  if ((!h->dscale && (rc = dalloc(&h->dscale, h->n))) || (!h->vals_s && (rc = dalloc(&h->vals_s, nz))) ||
+      (!h->vals32_s && (rc = dalloc(&h->vals32_s, nz))))
+    return rc;
+  DevState z{};
+  HIP_TRY(hipMemcpyAsync(h->st, &z, sizeof z, hipMemcpyHostToDevice, h->stream));
+  launch_jacobi_scale(h->n, h->rowptr, h->colind, h->vals, h->dscale, &h->st->status, h->stream);
+  HIP_TRY(hipGetLastError());
+  DevState out{};
+  if ((rc = read_state(h, &out))) return rc;
+  if (out.status != 0) return fail(BCG_EINVAL, "Jacobi preconditioner needs a positive finite diagonal entry in every row");
+  launch_scale_values(h->n, h->rowptr, h->colind, h->vals, h->dscale, h->vals_s, h->vals32_s, h->stream);
+  HIP_TRY(hipGetLastError());
+  return BCG_OK;
+}
+
 int validate_p(int variant, int k, int p, int* p_out) {
   if (k < 1 || k > 256) return fail(BCG_EINVAL, "k=%d outside 1..256", k);
   switch (variant) {
@@ -634,17 +663,43 @@ int bcg_solve(bcg_handle* h, const double* B, double* X, double tol, int maxit) 
   h->ref_r0.clear();
   h->host_ratios.assign(h->k, 1.0);
   int its = 0;
-  int rc = h->precision == BCG_FP32_REFINE ? solve_refine(h, B, X, tol, maxit) : solve_fp64(h, B, X, tol, maxit, nullptr, &its);
+  const double* Bsolve = B;
+  const bool jac = h->precond == BCG_PRECOND_JACOBI;
+  h->true_r0.clear();
+  if (jac) {
+    // ||B - A X0||_j for info.true_rel_res, then the scaled system:
+    // B <- D^{-1/2} B (a copy), X <- D^{1/2} X (in place), A <- D^{-1/2} A D^{-1/2}
+    int rc0;
+    if (!h->Bs && (rc0 = dalloc(&h->Bs, static_cast<size_t>(h->n) * h->k))) return rc0;
+    launch_residual(h->pl, h->rowptr, h->colind, h->vals, B, X, h->Q, nullptr, h->partN, 0, h->stream);
+    launch_reduce(h->pl, h->partN, h->rnew, h->pl.W, nullptr, h->stream);
+    HIP_TRY(hipGetLastError());
+    std::vector<double> n2;
+    if ((rc0 = fetch_norms(h, h->rnew, n2))) return rc0;
+    for (double v : n2) h->true_r0.push_back(std::sqrt(v));
+    launch_scale_rows(h->n, h->k, B, h->dscale, h->Bs, 0, h->stream);
+    launch_scale_rows(h->n, h->k, X, h->dscale, X, 1, h->stream);
+    std::swap(h->vals, h->vals_s);
+    std::swap(h->vals32, h->vals32_s);
+    Bsolve = h->Bs;
+  }
+  int rc = h->precision == BCG_FP32_REFINE ? solve_refine(h, Bsolve, X, tol, maxit)
+                                           : solve_fp64(h, Bsolve, X, tol, maxit, nullptr, &its);
+  if (jac) {
+    std::swap(h->vals, h->vals_s);
+    std::swap(h->vals32, h->vals32_s);
+    launch_scale_rows(h->n, h->k, X, h->dscale, X, 0, h->stream);  // X = D^{-1/2} Y
+  }
   if (h->precision != BCG_FP32_REFINE) h->info.iterations = its;
   const hipError_t se = hipStreamSynchronize(h->stream);
   if (se != hipSuccess && rc >= 0) rc = fail(BCG_EHIP, "solve failed: %s", hipGetErrorString(se));
   if (h->prof_on) prof_collect(h, 0);  // set-up launches still pending
-  // true residual of the returned X relative to ||R0_j||
+  // true residual of the returned X relative to ||R0_j|| (Euclidean)
   if (rc != BCG_EINVAL && rc != BCG_EHIP && rc != BCG_ENOMEM && (int)h->ref_r0.size() == h->k) {
     launch_residual(h->pl, h->rowptr, h->colind, h->vals, B, X, h->Q, nullptr, h->partN, 0, h->stream);
     launch_reduce(h->pl, h->partN, h->rnew, h->pl.W, nullptr, h->stream);
     std::vector<double> n2;
-    if (fetch_norms(h, h->rnew, n2) == BCG_OK) h->info.true_rel_res = max_ratio(n2, h->ref_r0);
+    if (fetch_norms(h, h->rnew, n2) == BCG_OK) h->info.true_rel_res = max_ratio(n2, jac ? h->true_r0 : h->ref_r0);
   }
   double m = 0.0;
   for (double v : h->host_ratios) m = std::max(m, v);
@@ -662,6 +717,26 @@ int bcg_update_values(bcg_handle* h, const double* values) {
   HIP_TRY(hipMemcpyAsync(h->vals, values, sizeof(double) * h->nnz, hipMemcpyDeviceToDevice, h->stream));
   launch_cast_values(h->nnz, h->vals, h->vals32, h->stream);
   HIP_TRY(hipGetLastError());
+  if (h->precond == BCG_PRECOND_JACOBI) {
+    const int rc = jacobi_prepare(h);
+    if (rc) {
+      h->precond = BCG_PRECOND_NONE;
+      return rc;
+    }
+  }
+  return BCG_OK;
+}
+
+int bcg_set_preconditioner(bcg_handle* h, int kind) {
+  if (!h) return fail(BCG_EINVAL, "handle is NULL");
+  if (kind != BCG_PRECOND_NONE && kind != BCG_PRECOND_JACOBI) return fail(BCG_EINVAL, "unknown preconditioner %d", kind);
+  DeviceGuard g(h->device);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->precond = BCG_PRECOND_NONE;
+  if (kind == BCG_PRECOND_NONE) return BCG_OK;
+  const int rc = jacobi_prepare(h);
+  if (rc) return rc;
+  h->precond = BCG_PRECOND_JACOBI;
   return BCG_OK;
 }
 

@@ -56,6 +56,7 @@ class BCG:
         self._h = h
         self.rowptr, self.colind = rowptr, colind
         self.precision = "fp64"
+        self.precond = "none"
 
     # -- configuration --------------------------------------------------
     def set_precision(self, mode: str = "fp64", inner_tol: float = 0.0, inner_maxit: int = 1000,
@@ -64,6 +65,16 @@ class BCG:
             raise BCGError(_capi.BCG_EINVAL, f"unknown precision {mode!r}")
         check(self._lib.bcg_set_precision(self._h, _capi.PRECISION[mode], inner_tol, inner_maxit, max_outer))
         self.precision = mode
+
+    def set_preconditioner(self, kind: str = "none") -> None:
+        """M of Algorithm 1: "none" (M = I) or "jacobi" (M = diag(A)); the stop
+        rule then uses M^{-1}-norms of the residual columns."""
+        if kind not in _capi.PRECOND:
+            raise BCGError(_capi.BCG_EINVAL, f"unknown preconditioner {kind!r}")
+        with torch.cuda.device(self.device):
+            self._bind_stream()
+            check(self._lib.bcg_set_preconditioner(self._h, _capi.PRECOND[kind]))
+        self.precond = kind
 
     def _bind_stream(self):
         check(self._lib.bcg_set_stream(self._h, _stream_ptr(self.device)))
