@@ -26,7 +26,10 @@ COMMON = [
 SOURCES = {
     "bcg_kernels.hip": [],
     "bcg_fast.hip": [],
-    "bcg_mfma.hip": [],
+    # matrix-core accumulators in ordinary vector registers: no copies
+    # through the accumulation registers around each product, and no spills
+    # in the width-64 passes
+    "bcg_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
     "bcg_solver.hip": [],
     # bit-exact face coefficients: every operation rounded once
     "bcg_stencil.hip": ["-ffp-contract=off"],

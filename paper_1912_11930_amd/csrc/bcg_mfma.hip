@@ -260,17 +260,22 @@ template <int D>
 __device__ __forceinline__ float xor4(float x) {
   return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), ((4 * D) << 10) | 0x1F));
 }
-__device__ __forceinline__ float pick4(const float (&v)[4], int i) {
-  return i == 0 ? v[0] : i == 1 ? v[1] : i == 2 ? v[2] : v[3];
+// a_i selected by the two bits of i, on values: two levels of selects. (A
+// compare chain compiles to branches, and selects between elements of one
+// array can be folded into an indexed access that moves the array to LDS.)
+__device__ __forceinline__ float sel4(float a0, float a1, float a2, float a3, int i) {
+  const float lo = (i & 1) ? a1 : a0, hi = (i & 1) ? a3 : a2;
+  return (i & 2) ? hi : lo;
 }
 __device__ __forceinline__ void transpose4(const float (&v)[4], float (&w)[4], int t) {
-  const float s1 = xor4<1>(pick4(v, t ^ 1)), s2 = xor4<2>(pick4(v, t ^ 2)), s3 = xor4<3>(pick4(v, t ^ 3));
-  const float own = pick4(v, t);
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int d = m ^ t;
-    w[m] = d == 0 ? own : d == 1 ? s1 : d == 2 ? s2 : s3;
-  }
+  const float v0 = v[0], v1 = v[1], v2 = v[2], v3 = v[3];
+  const float s1 = xor4<1>(sel4(v0, v1, v2, v3, t ^ 1)), s2 = xor4<2>(sel4(v0, v1, v2, v3, t ^ 2)),
+              s3 = xor4<3>(sel4(v0, v1, v2, v3, t ^ 3));
+  const float own = sel4(v0, v1, v2, v3, t);
+  w[0] = sel4(own, s1, s2, s3, t);
+  w[1] = sel4(own, s1, s2, s3, t ^ 1);
+  w[2] = sel4(own, s1, s2, s3, t ^ 2);
+  w[3] = sel4(own, s1, s2, s3, t ^ 3);
 }
 
 // Row layouts of a 16 x 16 tile for 2- or 4-element row accesses. A result
@@ -613,6 +618,26 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restric
 }
 
 // ---------------------------------------------------------------- SpMM
+// Element access at base + e. With O32 every byte offset into the operands
+// fits in 32 bits, and the access is a uniform 64-bit base plus a 32-bit lane
+// offset: one address operation per access instead of 64-bit arithmetic.
+template <bool O32>
+using EIdx = typename std::conditional<O32, uint32_t, int64_t>::type;
+template <bool O32, typename V, typename E>
+__device__ __forceinline__ V ld_at(const E* base, EIdx<O32> e) {
+  if constexpr (O32)
+    return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + e * static_cast<uint32_t>(sizeof(E)));
+  else
+    return *reinterpret_cast<const V*>(base + e);
+}
+template <bool O32, typename V, typename E>
+__device__ __forceinline__ void st_at(E* base, EIdx<O32> e, const V& v) {
+  if constexpr (O32)
+    *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + e * static_cast<uint32_t>(sizeof(E))) = v;
+  else
+    *reinterpret_cast<V*>(base + e) = v;
+}
+
 // Q = A P with the partial alpha = <<P, Q>>. A wave takes steps of 8 rows of
 // its column group, 8 lanes per row: lane l holds columns 2(l&7), 2(l&7)+1 of
 // each 16-column block of row (l>>3) (16-byte gathers). One exchange between
@@ -673,7 +698,7 @@ __device__ __forceinline__ void spread8(Row8<T>& r, int c, T v) {
   }
 }
 
-template <typename T, int K, int PW>
+template <typename T, int K, int PW, bool O32>
 __global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __restrict__ rowptr,
                                                       const int32_t* __restrict__ colind, const T* __restrict__ vals,
                                                       const T* __restrict__ Pm, T* __restrict__ Q,
@@ -692,33 +717,34 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __
   MAcc<NB> acc;
   acc.zero();
   const int32_t* __restrict__ sched = pl.sched;
-  auto row_of = [&](int64_t step) -> int64_t {
+  using E = EIdx<O32>;
+  auto row_of = [&](int64_t step) -> int {
     int64_t e = step * 8 + rr;
     e = e < n ? e : n - 1;
-    return sched ? static_cast<int64_t>(sched[e]) : e;
+    return sched ? ld_at<O32, int32_t>(sched, static_cast<E>(e)) : static_cast<int>(e);
   };
   // entry j0 + cg (clamped into the row; the value of an entry past j1 is 0,
   // so its product adds nothing)
   auto idx_load = [&](int j0, int j1, int& c, T& v) {
     const int jj = max(min(j0 + cg, j1 - 1), 0);
-    c = colind[jj];
-    const T x = vals[jj];
+    c = ld_at<O32, int32_t>(colind, static_cast<E>(jj));
+    const T x = ld_at<O32, T>(vals, static_cast<E>(jj));
     v = j0 + cg < j1 ? x : T(0);
   };
   const int64_t tw = ww.stride;
   const int64_t last = ww.end > ww.first ? ww.end - 1 : ww.first;
   int64_t s = ww.first;
   Row8<T> cur;
-  int64_t cur_row = 0, row1 = 0, row2 = 0;
+  int cur_row = 0, row1 = 0, row2 = 0;
   int nj0 = 0, nj1 = 0;  // CSR range of step s + tw
   if (s < ww.end) {
     cur_row = row_of(s);
     row1 = row_of(min(s + tw, last));
     row2 = row_of(min(s + 2 * tw, last));
-    cur.j0 = rowptr[cur_row];
-    cur.j1 = rowptr[cur_row + 1];
-    nj0 = rowptr[row1];
-    nj1 = rowptr[row1 + 1];
+    cur.j0 = ld_at<O32, int32_t>(rowptr, static_cast<E>(cur_row));
+    cur.j1 = ld_at<O32, int32_t>(rowptr, static_cast<E>(cur_row) + 1);
+    nj0 = ld_at<O32, int32_t>(rowptr, static_cast<E>(row1));
+    nj1 = ld_at<O32, int32_t>(rowptr, static_cast<E>(row1) + 1);
     int c;
     T v;
     idx_load(cur.j0, cur.j1, c, v);
@@ -726,14 +752,14 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __
   }
   for (; s < ww.end; s += tw) {
     const bool ok = s * 8 + rr < n;
-    const int64_t i = cur_row;
+    const E i = static_cast<E>(cur_row);
     // 1. gathers of the current step (first block) and the own row of P
     T2 xv[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) xv[u] = *reinterpret_cast<const T2*>(Pm + (int64_t)cur.cols[u] * K + c0);
+    for (int u = 0; u < 8; ++u) xv[u] = ld_at<O32, T2>(Pm, static_cast<E>(cur.cols[u]) * K + c0);
     T2 pv[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) pv[b] = *reinterpret_cast<const T2*>(Pm + i * K + c0 + 16 * b);
+    for (int b = 0; b < NB; ++b) pv[b] = ld_at<O32, T2>(Pm, i * K + c0 + 16 * b);
     // 2. index chunk of the next step
     Row8<T> nxt;
     nxt.j0 = nj0;
@@ -742,9 +768,9 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __
     T nv;
     idx_load(nj0, nj1, nc, nv);
     // 3. CSR range two steps ahead, schedule entry three steps ahead
-    nj0 = rowptr[row2];
-    nj1 = rowptr[row2 + 1];
-    const int64_t row3 = row_of(min(s + 3 * tw, last));
+    nj0 = ld_at<O32, int32_t>(rowptr, static_cast<E>(row2));
+    nj1 = ld_at<O32, int32_t>(rowptr, static_cast<E>(row2) + 1);
+    const int row3 = row_of(min(s + 3 * tw, last));
     // 4. consume the gathers, block by block
     T q[NB][2];
 #pragma unroll
@@ -752,7 +778,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __
       if (b > 0) {
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-          xv[u] = *reinterpret_cast<const T2*>(Pm + (int64_t)cur.cols[u] * K + c0 + 16 * b);
+          xv[u] = ld_at<O32, T2>(Pm, static_cast<E>(cur.cols[u]) * K + c0 + 16 * b);
       }
       T q0 = T(0), q1 = T(0);
 #pragma unroll
@@ -774,7 +800,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __
       for (int b = 0; b < NB; ++b) {
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-          xv[u] = *reinterpret_cast<const T2*>(Pm + (int64_t)ex.cols[u] * K + c0 + 16 * b);
+          xv[u] = ld_at<O32, T2>(Pm, static_cast<E>(ex.cols[u]) * K + c0 + 16 * b);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           q[b][0] = fma(ex.vs[u], xv[u].x, q[b][0]);
@@ -786,7 +812,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __
     double pe[NB][2], qe[NB][2];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      if (ok) *reinterpret_cast<T2*>(Q + i * K + c0 + 16 * b) = T2{q[b][0], q[b][1]};
+      if (ok) st_at<O32>(Q, i * K + c0 + 16 * b, T2{q[b][0], q[b][1]});
       const double p0 = ok ? static_cast<double>(pv[b].x) : 0.0, p1 = ok ? static_cast<double>(pv[b].y) : 0.0;
       const double q0 = ok ? static_cast<double>(q[b][0]) : 0.0, q1 = ok ? static_cast<double>(q[b][1]) : 0.0;
       const double pr = dpp_ror8(odd ? p0 : p1), qr = dpp_ror8(odd ? q0 : q1);
@@ -819,7 +845,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __
 // 4s + m (s = l>>4, m = 0..3): the operands of four 16x16x4 products.
 template <int I>
 __device__ __forceinline__ int quad_bcast(int x) {
-  return __builtin_amdgcn_update_dpp(0, x, I * 0x55, 0xF, 0xF, false);  // quad_perm [I,I,I,I]
+  return __builtin_amdgcn_mov_dpp(x, I * 0x55, 0xF, 0xF, false);  // quad_perm [I,I,I,I]
 }
 template <int I>
 __device__ __forceinline__ float quad_bcast(float x) {
@@ -848,7 +874,7 @@ __device__ __forceinline__ void spread_quad(Row8f& r, const int (&c)[2], const f
   }
 }
 
-template <int K, int PW>
+template <int K, int PW, bool O32>
 __global__ __launch_bounds__(kBlock) void k_spmm_mfma_f32(Plan pl, const int32_t* __restrict__ rowptr,
                                                           const int32_t* __restrict__ colind,
                                                           const float* __restrict__ vals, const float* __restrict__ Pm,
@@ -866,10 +892,11 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma_f32(Plan pl, const int32_t
   MAcc<NB> acc;
   acc.zero();
   const int32_t* __restrict__ sched = pl.sched;
-  auto row_of = [&](int64_t step) -> int64_t {
+  using E = EIdx<O32>;
+  auto row_of = [&](int64_t step) -> int {
     int64_t e = step * 16 + rr;
     e = e < n ? e : n - 1;
-    return sched ? static_cast<int64_t>(sched[e]) : e;
+    return sched ? ld_at<O32, int32_t>(sched, static_cast<E>(e)) : static_cast<int>(e);
   };
   // entries j0 + cq and j0 + cq + 4 (clamped into the row; past j1 the value
   // is 0, so the product adds nothing)
@@ -877,8 +904,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma_f32(Plan pl, const int32_t
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int jj = max(min(j0 + cq + 4 * h, j1 - 1), 0);
-      c[h] = colind[jj];
-      const float x = vals[jj];
+      c[h] = ld_at<O32, int32_t>(colind, static_cast<E>(jj));
+      const float x = ld_at<O32, float>(vals, static_cast<E>(jj));
       v[h] = j0 + cq + 4 * h < j1 ? x : 0.f;
     }
   };
@@ -886,16 +913,16 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma_f32(Plan pl, const int32_t
   const int64_t last = ww.end > ww.first ? ww.end - 1 : ww.first;
   int64_t s = ww.first;
   Row8f cur;
-  int64_t cur_row = 0, row1 = 0, row2 = 0;
+  int cur_row = 0, row1 = 0, row2 = 0;
   int nj0 = 0, nj1 = 0;
   if (s < ww.end) {
     cur_row = row_of(s);
     row1 = row_of(min(s + tw, last));
     row2 = row_of(min(s + 2 * tw, last));
-    cur.j0 = rowptr[cur_row];
-    cur.j1 = rowptr[cur_row + 1];
-    nj0 = rowptr[row1];
-    nj1 = rowptr[row1 + 1];
+    cur.j0 = ld_at<O32, int32_t>(rowptr, static_cast<E>(cur_row));
+    cur.j1 = ld_at<O32, int32_t>(rowptr, static_cast<E>(cur_row) + 1);
+    nj0 = ld_at<O32, int32_t>(rowptr, static_cast<E>(row1));
+    nj1 = ld_at<O32, int32_t>(rowptr, static_cast<E>(row1) + 1);
     int c[2];
     float v[2];
     idx_load(cur.j0, cur.j1, c, v);
@@ -903,29 +930,29 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma_f32(Plan pl, const int32_t
   }
   for (; s < ww.end; s += tw) {
     const bool ok = s * 16 + rr < n;
-    const int64_t i = cur_row;
+    const E i = static_cast<E>(cur_row);
     float4 xv[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) xv[u] = *reinterpret_cast<const float4*>(Pm + (int64_t)cur.cols[u] * K + c0);
+    for (int u = 0; u < 8; ++u) xv[u] = ld_at<O32, float4>(Pm, static_cast<E>(cur.cols[u]) * K + c0);
     float4 pv[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) pv[b] = *reinterpret_cast<const float4*>(Pm + i * K + c0 + 16 * b);
+    for (int b = 0; b < NB; ++b) pv[b] = ld_at<O32, float4>(Pm, i * K + c0 + 16 * b);
     Row8f nxt;
     nxt.j0 = nj0;
     nxt.j1 = nj1;
     int nc[2];
     float nv[2];
     idx_load(nj0, nj1, nc, nv);
-    nj0 = rowptr[row2];
-    nj1 = rowptr[row2 + 1];
-    const int64_t row3 = row_of(min(s + 3 * tw, last));
+    nj0 = ld_at<O32, int32_t>(rowptr, static_cast<E>(row2));
+    nj1 = ld_at<O32, int32_t>(rowptr, static_cast<E>(row2) + 1);
+    const int row3 = row_of(min(s + 3 * tw, last));
     float q[NB][4];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       if (b > 0) {
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-          xv[u] = *reinterpret_cast<const float4*>(Pm + (int64_t)cur.cols[u] * K + c0 + 16 * b);
+          xv[u] = ld_at<O32, float4>(Pm, static_cast<E>(cur.cols[u]) * K + c0 + 16 * b);
       }
       float a[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -947,7 +974,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma_f32(Plan pl, const int32_t
       for (int b = 0; b < NB; ++b) {
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-          xv[u] = *reinterpret_cast<const float4*>(Pm + (int64_t)ex.cols[u] * K + c0 + 16 * b);
+          xv[u] = ld_at<O32, float4>(Pm, static_cast<E>(ex.cols[u]) * K + c0 + 16 * b);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const float x[4] = {xv[u].x, xv[u].y, xv[u].z, xv[u].w};
@@ -959,7 +986,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma_f32(Plan pl, const int32_t
     double pt[NB][4], qt[NB][4];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      if (ok) *reinterpret_cast<float4*>(Q + i * K + c0 + 16 * b) = float4{q[b][0], q[b][1], q[b][2], q[b][3]};
+      if (ok) st_at<O32>(Q, i * K + c0 + 16 * b, float4{q[b][0], q[b][1], q[b][2], q[b][3]});
       const float pz[4] = {ok ? pv[b].x : 0.f, ok ? pv[b].y : 0.f, ok ? pv[b].z : 0.f, ok ? pv[b].w : 0.f};
       const float qz[4] = {ok ? q[b][0] : 0.f, ok ? q[b][1] : 0.f, ok ? q[b][2] : 0.f, ok ? q[b][3] : 0.f};
       transpose4(pz, pt[b], tq);
@@ -1088,13 +1115,28 @@ void launch_spmm_mfma(const Plan& pl, const int32_t* rowptr, const int32_t* coli
   const int prec = std::is_same<T, float>::value ? 1 : 0;
   if (pl.sp_chunk[prec] == 0) check_grid(pl);
   const dim3 grid(pl.sp_nwg[prec]);
+  // 32-bit byte offsets when the vectors, the entries and the row pointers
+  // all stay below 4 GiB
+  const int64_t lim = int64_t(1) << 32;
+  const bool o32 = pl.n * pl.k * static_cast<int64_t>(sizeof(T)) < lim &&
+                   pl.nnz * static_cast<int64_t>(sizeof(T)) < lim && (pl.n + 1) * 4 < lim;
   dispatch_mfma(pl, [&](auto Kc, auto Wc) {
-    if constexpr (std::is_same<T, float>::value)
-      hipLaunchKernelGGL((k_spmm_mfma_f32<decltype(Kc)::value, decltype(Wc)::value>), grid, dim3(kBlock), 0, s, pl,
-                         rowptr, colind, vals, P, Q, part, st);
-    else
-      hipLaunchKernelGGL((k_spmm_mfma<T, decltype(Kc)::value, decltype(Wc)::value>), grid, dim3(kBlock), 0, s, pl,
-                         rowptr, colind, vals, P, Q, part, st);
+    constexpr int K = decltype(Kc)::value, W = decltype(Wc)::value;
+    if constexpr (std::is_same<T, float>::value) {
+      if (o32)
+        hipLaunchKernelGGL((k_spmm_mfma_f32<K, W, true>), grid, dim3(kBlock), 0, s, pl, rowptr, colind, vals, P, Q,
+                           part, st);
+      else
+        hipLaunchKernelGGL((k_spmm_mfma_f32<K, W, false>), grid, dim3(kBlock), 0, s, pl, rowptr, colind, vals, P, Q,
+                           part, st);
+    } else {
+      if (o32)
+        hipLaunchKernelGGL((k_spmm_mfma<T, K, W, true>), grid, dim3(kBlock), 0, s, pl, rowptr, colind, vals, P, Q,
+                           part, st);
+      else
+        hipLaunchKernelGGL((k_spmm_mfma<T, K, W, false>), grid, dim3(kBlock), 0, s, pl, rowptr, colind, vals, P, Q,
+                           part, st);
+    }
   });
 }
 
