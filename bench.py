@@ -220,6 +220,9 @@ def main() -> int:
                     help="row order of the sparse product: 32x32 x-y tiles swept through z (3D), or natural")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (counter calibration)")
+    ap.add_argument("--study", default=None, choices=["repeat128"],
+                    help="repeat128: time to solve 128 right-hand sides in 128/k solves, k = 16..128, p = 16")
+    ap.add_argument("--study-precisions", default="fp32_refine,fp64")
     ap.add_argument("--traffic-from", default=None,
                     help="write profiles/traffic.json from rocprofv3 --pmc databases in this folder")
     args = ap.parse_args()
@@ -228,6 +231,11 @@ def main() -> int:
     if args.traffic_from:
         return traffic_from(args.traffic_from, args.workload, args.variant)
 
+    if args.study == "repeat128":
+        if args.gpus != 1:
+            log("bench.py: only --gpus 1 is supported")
+            return 2
+        return repeat_study(args)
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
@@ -358,6 +366,70 @@ def main() -> int:
         out["cpu_baseline"] = cpu_baseline(w, args.variant, p_eff, head_fp64_iterations(out), args.cpu_budget,
                                            args.precond)
     print(json.dumps(out), flush=True)
+    return 0
+
+
+def repeat_study(args) -> int:
+    """Time to solve 128 right-hand sides of the 128^3 Poisson system in
+    r = 128/k solves of k columns each, k = 16, 32, 64, 128 with p = 16
+    (block at k = 16, hybrid above): the paper's third experiment (Section 5),
+    on this GPU. One JSON line per (precision, k): the wall time of the r
+    solves after one warm-up solve, iterations and the worst true relative
+    residual of the r solves, and from one more solve with per-class events
+    the sparse product's and the updates' average time and algorithmic GB/s."""
+    import torch
+
+    import paper_1912_11930_amd as P
+    from workload import WORKLOADS, rhs
+
+    w = WORKLOADS["poisson3d_128_k16"]
+    total = 128
+    dev = torch.device("cuda:0")
+    rp, ci, va = P.stencil(w.dim, w.N, None, device=dev)
+    sched = P.stencil_schedule(w.dim, w.N, 32, device=dev)
+    B_all = torch.from_numpy(rhs(w.n, total, "uniform")).to(dev)
+    n, nnz = w.n, w.nnz
+    for precision in args.study_precisions.split(","):
+        for k in (16, 32, 64, 128):
+            variant, p = ("block", 0) if k == 16 else ("hybrid", 16)
+            solver = P.BCG(rp, ci, va, k=k, subalgebra=variant, p=p)
+            solver.set_row_schedule(sched)
+            solver.set_precision(precision)
+            batches = [B_all[:, j * k:(j + 1) * k].contiguous() for j in range(total // k)]
+            X = torch.zeros_like(batches[0])
+            _, info = solver.solve(batches[0], X, tol=w.tol, maxit=100000)  # warm-up
+            X.zero_()
+            solver.set_profiling(True)
+            solver.solve(batches[0], X, tol=w.tol, maxit=100000)
+            times = solver.kernel_times()
+            solver.set_profiling(False)
+            its, worst = [], 0.0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for Bj in batches:
+                X.zero_()
+                _, info = solver.solve(Bj, X, tol=w.tol, maxit=100000)
+                if info["status_name"] != "OK":
+                    log(f"study: k={k} {precision}: status {info['status_name']}")
+                    return 1
+                its.append(info["iterations"])
+                worst = max(worst, info["true_rel_res"])
+            torch.cuda.synchronize()
+            elapsed = time.perf_counter() - t0
+            kernels = {}
+            for c in ("spmm", "update_r", "update_xp"):
+                launches, ms = times[c]
+                if launches:
+                    us = 1e3 * ms / launches
+                    kernels[c] = {"avg_us": round(us, 2),
+                                  "GBps": round(algorithmic_bytes(c, n, nnz, k, precision) / (us * 1e-6) / 1e9, 1)}
+            line = {"study": "repeat128", "workload": f"{w.name.rsplit('_k', 1)[0]}_rhs128", "total_rhs": total,
+                    "k": k, "p": 16, "variant": variant, "solves": len(batches), "precision": precision,
+                    "seconds": round(elapsed, 4), "rhs_per_s": round(total / elapsed, 2),
+                    "iterations": its, "max_true_rel_res": worst, "kernels": kernels}
+            print(json.dumps(line), flush=True)
+            del solver, X, batches
+            torch.cuda.empty_cache()
     return 0
 
 

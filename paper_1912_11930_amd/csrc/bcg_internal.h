@@ -59,6 +59,7 @@ struct Plan {
   int nwg;      // workgroups of the row kernels
   int fast;     // 1: the k-specialised row kernels apply (k in {8..128}, p <= 16)
   int mfma;     // column-group width of the matrix-core row kernels (0: not used)
+  int sp_w;     // column-group width of the matrix-core sparse product
   // sparse product of the matrix-core path, per precision (0: FP64, 1: FP32):
   // workgroups and steps per wave of its chunked grid (0 steps: persistent
   // grid of nwg workgroups)
@@ -72,6 +73,8 @@ bool fast_supported(const Plan& pl);
 // matrix-core row kernels: group width for (nnz, k, p), 0 where they do not
 // apply; workgroup count that gives every XCD a wave per column group
 int mfma_width(int64_t nnz, int k, int p);
+// matrix-core sparse-product group width for row-kernel width w
+int mfma_sp_width(int k, int w, int p);
 int mfma_grid(int64_t n, int k, int w);
 // chunked sparse-product grid of the matrix-core path (sets sp_nwg, sp_chunk)
 void mfma_sp_grid(Plan& pl);

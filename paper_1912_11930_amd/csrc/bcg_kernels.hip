@@ -1519,6 +1519,7 @@ Plan make_plan(int64_t n, int64_t nnz, int k, int p, int global, int dec) {
   pl.nwg = static_cast<int>(nwg < 1 ? 1 : nwg);
   pl.fast = fast_supported(pl);
   pl.mfma = mfma_width(nnz, k, p);
+  pl.sp_w = pl.mfma ? mfma_sp_width(k, pl.mfma, p) : 0;
   if (pl.mfma) {
     pl.nwg = mfma_grid(n, k, pl.mfma);
     mfma_sp_grid(pl);

@@ -934,6 +934,14 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma_f32(Plan pl, const int32_t
     float4 xv[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) xv[u] = ld_at<O32, float4>(Pm, static_cast<E>(cur.cols[u]) * K + c0);
+    // two-block groups: the second block's gathers go out with the first's
+    // (wider groups reload per block to stay within the registers)
+    constexpr bool UP = NB == 2;
+    float4 xw[UP ? 8 : 1];
+    if constexpr (UP) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xw[u] = ld_at<O32, float4>(Pm, static_cast<E>(cur.cols[u]) * K + c0 + 16);
+    }
     float4 pv[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) pv[b] = ld_at<O32, float4>(Pm, i * K + c0 + 16 * b);
@@ -950,9 +958,14 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma_f32(Plan pl, const int32_t
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       if (b > 0) {
+        if constexpr (UP) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          xv[u] = ld_at<O32, float4>(Pm, static_cast<E>(cur.cols[u]) * K + c0 + 16 * b);
+          for (int u = 0; u < 8; ++u) xv[u] = xw[u];
+        } else {
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            xv[u] = ld_at<O32, float4>(Pm, static_cast<E>(cur.cols[u]) * K + c0 + 16 * b);
+        }
       }
       float a[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -1014,8 +1027,7 @@ int env_set(const char* name) {
 }
 
 template <typename F>
-bool dispatch_mfma(const Plan& pl, F&& f) {
-  const int w = pl.mfma;
+bool dispatch_mfma_w(int k, int w, F&& f) {
   if (!w) return false;
   auto withK = [&](auto Kc) -> bool {
     constexpr int K = decltype(Kc)::value;
@@ -1035,7 +1047,7 @@ bool dispatch_mfma(const Plan& pl, F&& f) {
       }
     return false;
   };
-  switch (pl.k) {
+  switch (k) {
     case 16: return withK(std::integral_constant<int, 16>());
     case 32: return withK(std::integral_constant<int, 32>());
     case 48: return withK(std::integral_constant<int, 48>());
@@ -1050,13 +1062,28 @@ bool dispatch_mfma(const Plan& pl, F&& f) {
 
 // the launch must give every XCD (or the whole grid below 8 workgroups) at
 // least one wave per column group
-void check_grid(const Plan& pl) {
-  const int ng = pl.k / pl.mfma;
+template <typename F>
+bool dispatch_mfma(const Plan& pl, F&& f) {
+  return dispatch_mfma_w(pl.k, pl.mfma, f);
+}
+
+void check_grid(const Plan& pl, int w) {
+  const int ng = pl.k / w;
   const int min_waves = pl.nwg < 8 ? pl.nwg * 4 : (pl.nwg / 8) * 4;
   if (min_waves < ng) throw std::runtime_error("matrix-core launch: fewer waves than column groups");
 }
 
 }  // namespace
+
+// The sparse product takes groups of 32 columns where k allows (p then
+// divides 32, and each group's p x p Gram blocks lie on the diagonal of its
+// 32 x 32 product): one wave gathers both 16-column halves of a row with one
+// set of index loads, where two waves of 16 columns each load them twice.
+// Measured 5-24 % faster for k = 32..128.
+int mfma_sp_width(int k, int w, int p) {
+  if (w == 16 && k % 32 == 0 && 32 % p == 0) return 32;
+  return w;
+}
 
 int mfma_width(int64_t nnz, int k, int p) {
   if (env_set("BCG_NO_MFMA") || env_set("BCG_GENERIC_ONLY") || nnz < 1) return 0;
@@ -1068,7 +1095,7 @@ int mfma_width(int64_t nnz, int k, int p) {
 }
 
 void mfma_sp_grid(Plan& pl) {
-  const int w = pl.mfma, ng = pl.k / w;
+  const int w = pl.sp_w, ng = pl.k / w;
   const bool share = ng <= 4 && 4 % ng == 0;
   const int ngb = share ? 1 : (ng + 3) / 4, wpg = share ? 4 / ng : 1;
   const int kwg = share ? pl.k : 4 * w;  // columns one workgroup covers
@@ -1113,14 +1140,14 @@ template <typename T>
 void launch_spmm_mfma(const Plan& pl, const int32_t* rowptr, const int32_t* colind, const T* vals, const T* P, T* Q,
                       double* part, const DevState* st, hipStream_t s) {
   const int prec = std::is_same<T, float>::value ? 1 : 0;
-  if (pl.sp_chunk[prec] == 0) check_grid(pl);
+  if (pl.sp_chunk[prec] == 0) check_grid(pl, pl.sp_w);
   const dim3 grid(pl.sp_nwg[prec]);
   // 32-bit byte offsets when the vectors, the entries and the row pointers
   // all stay below 4 GiB
   const int64_t lim = int64_t(1) << 32;
   const bool o32 = pl.n * pl.k * static_cast<int64_t>(sizeof(T)) < lim &&
                    pl.nnz * static_cast<int64_t>(sizeof(T)) < lim && (pl.n + 1) * 4 < lim;
-  dispatch_mfma(pl, [&](auto Kc, auto Wc) {
+  dispatch_mfma_w(pl.k, pl.sp_w, [&](auto Kc, auto Wc) {
     constexpr int K = decltype(Kc)::value, W = decltype(Wc)::value;
     if constexpr (std::is_same<T, float>::value) {
       if (o32)
@@ -1143,7 +1170,7 @@ void launch_spmm_mfma(const Plan& pl, const int32_t* rowptr, const int32_t* coli
 template <typename T>
 void launch_update_r_mfma(const Plan& pl, T* R, const T* Q, const T* lam, double* part, const DevState* st,
                           hipStream_t s) {
-  check_grid(pl);
+  check_grid(pl, pl.mfma);
   dispatch_mfma(pl, [&](auto Kc, auto Wc) {
     hipLaunchKernelGGL((k_update_r_mfma<T, decltype(Kc)::value, decltype(Wc)::value>), dim3(pl.nwg), dim3(kBlock), 0,
                        s, pl, R, Q, lam, part, st);
@@ -1153,7 +1180,7 @@ void launch_update_r_mfma(const Plan& pl, T* R, const T* Q, const T* lam, double
 template <typename T>
 void launch_update_xp_mfma(const Plan& pl, T* X, T* P, const T* R, const T* lam, const T* beta, double* part,
                            const DevState* st, hipStream_t s) {
-  check_grid(pl);
+  check_grid(pl, pl.mfma);
   dispatch_mfma(pl, [&](auto Kc, auto Wc) {
     hipLaunchKernelGGL((k_update_xp_mfma<T, decltype(Kc)::value, decltype(Wc)::value>), dim3(pl.nwg), dim3(kBlock),
                        0, s, pl, X, P, R, lam, beta, part, st);
