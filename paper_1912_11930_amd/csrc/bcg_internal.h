@@ -65,6 +65,7 @@ struct Plan {
   // grid of nwg workgroups)
   int sp_nwg[2];
   int sp_chunk[2];
+  int sp_o32[2];  // sparse product with 32-bit lane offsets (FP64, FP32)
   const int32_t* sched;  // processing order of the sparse-product rows (nullptr: natural)
 };
 

@@ -1120,6 +1120,11 @@ void mfma_sp_grid(Plan& pl) {
     }
     pl.sp_chunk[prec] = chunk;
     pl.sp_nwg[prec] = static_cast<int>(8 * ngb * nch);
+    // 32-bit byte offsets when the vectors, the entries and the row pointers
+    // all stay below 4 GiB (BCG_WIDE_OFFSETS forces 64-bit offsets)
+    const int64_t lim = int64_t(1) << 32;
+    pl.sp_o32[prec] = pl.n * pl.k * elem < lim && pl.nnz * elem < lim && (pl.n + 1) * 4 < lim &&
+                      !env_set("BCG_WIDE_OFFSETS");
   }
 }
 
@@ -1142,11 +1147,7 @@ void launch_spmm_mfma(const Plan& pl, const int32_t* rowptr, const int32_t* coli
   const int prec = std::is_same<T, float>::value ? 1 : 0;
   if (pl.sp_chunk[prec] == 0) check_grid(pl, pl.sp_w);
   const dim3 grid(pl.sp_nwg[prec]);
-  // 32-bit byte offsets when the vectors, the entries and the row pointers
-  // all stay below 4 GiB
-  const int64_t lim = int64_t(1) << 32;
-  const bool o32 = pl.n * pl.k * static_cast<int64_t>(sizeof(T)) < lim &&
-                   pl.nnz * static_cast<int64_t>(sizeof(T)) < lim && (pl.n + 1) * 4 < lim;
+  const bool o32 = pl.sp_o32[prec] != 0;
   dispatch_mfma_w(pl.k, pl.sp_w, [&](auto Kc, auto Wc) {
     constexpr int K = decltype(Kc)::value, W = decltype(Wc)::value;
     if constexpr (std::is_same<T, float>::value) {

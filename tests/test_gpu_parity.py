@@ -242,6 +242,24 @@ def test_fast_path_fixed_iterations(monkeypatch, k, variant, p, path):
     assert rel(host(Xg), Xo) <= FIXED_TOL
 
 
+@pytest.mark.parametrize("k,variant,p", [(16, "block", 0), (32, "block", 0), (32, "hybrid", 16), (64, "hybrid", 8),
+                                         (128, "global", 4)])
+def test_wide_offsets_fixed_iterations(monkeypatch, k, variant, p):
+    # the sparse products' 64-bit offset form, which systems whose operands
+    # exceed 4 GiB take (forced here on a small one)
+    monkeypatch.setenv("BCG_WIDE_OFFSETS", "1")
+    log(f"wide offsets k={k} {variant} p={p}")
+    N = 41 if k <= 32 else 19
+    A = stencil_csr(2, N, cell_coefficients(2, N, 0.8))
+    B = rhs(A.shape[0], k, "normal", seed=300 + k)
+    m = 8
+    Xo, io = oracle_solve(A, B, variant, p, tol=0.0, maxit=m)
+    s = _solver(A, k, variant, p)
+    Xg, ig = s.solve(dev(B), tol=0.0, maxit=m)
+    assert ig["iterations"] == io["iterations"] == m
+    assert rel(host(Xg), Xo) <= FIXED_TOL
+
+
 @pytest.mark.parametrize("k,variant,p", [(8, "block", 0), (16, "hybrid", 4), (64, "hybrid", 8), (128, "global", 1)])
 def test_generic_path_forced(monkeypatch, k, variant, p):
     # the generic LDS-tiled kernels stay correct for shapes the fast path also covers

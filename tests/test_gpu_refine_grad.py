@@ -58,7 +58,7 @@ FP32_CASES = [(16, "block", 0), (16, "hybrid", 4), (16, "parallel", 1), (32, "bl
               (48, "hybrid", 16), (8, "hybrid", 4), (12, "hybrid", 3)]
 
 
-@pytest.mark.parametrize("path", ["default", "no_mfma"])
+@pytest.mark.parametrize("path", ["default", "no_mfma", "wide_offsets"])
 @pytest.mark.parametrize("k,variant,p", FP32_CASES)
 def test_fp32_inner_iterations_match_oracle(monkeypatch, k, variant, p, path):
     """One refinement step with 6 FP32 inner iterations against the oracle's.
@@ -69,6 +69,8 @@ def test_fp32_inner_iterations_match_oracle(monkeypatch, k, variant, p, path):
     """
     if path == "no_mfma":
         monkeypatch.setenv("BCG_NO_MFMA", "1")
+    if path == "wide_offsets":  # 64-bit offsets in the sparse products
+        monkeypatch.setenv("BCG_WIDE_OFFSETS", "1")
     from oracle import refine
     log(f"fp32 inner k={k} {variant} p={p} {path}")
     P = _P()
