@@ -66,6 +66,7 @@ struct Plan {
   int sp_nwg[2];
   int sp_chunk[2];
   int sp_o32[2];  // sparse product with 32-bit lane offsets (FP64, FP32)
+  int nt[2];      // row kernels stream dead operands non-temporally (FP64, FP32)
   const int32_t* sched;  // processing order of the sparse-product rows (nullptr: natural)
 };
 

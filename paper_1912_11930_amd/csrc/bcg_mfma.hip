@@ -40,6 +40,13 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
+// Whether the row kernels may load an operand stream non-temporally: only
+// where a wave's row slices cover whole 128-byte lines (see Lay).
+template <typename T, int K, int PW>
+constexpr bool stream_nt() {
+  return K == PW || (PW * static_cast<int>(sizeof(T))) % 128 == 0;
+}
+
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -220,9 +227,10 @@ struct Coeff {
 
 // A operand of block ab: lane l holds row (l & 15) of the tile at the
 // columns coeff_row gives for k-steps kk = 0..3 (FP64: two 16-byte loads,
-// FP32: one). Rows past n read row n-1 and are zeroed. Loaded non-temporally:
-// the operand (Q in the R update, the old P in the X/P pass) is dead after it.
-template <typename T, int K, int PW>
+// FP32: one). Rows past n read row n-1 and are zeroed. Non-temporal where
+// stream_nt allows: the operand (Q in the R update, the old P in the X/P
+// pass) is dead after it.
+template <typename T, int K, int PW, bool NT>
 __device__ __forceinline__ void load_a(double (&a)[4], const T* __restrict__ X, int64_t row0, int64_t n, int G, int ab,
                                        int lane) {
   const int64_t r = row0 + (lane & 15);
@@ -230,15 +238,25 @@ __device__ __forceinline__ void load_a(double (&a)[4], const T* __restrict__ X, 
   const int64_t rc = ok ? r : n - 1;
   if constexpr (sizeof(T) == 8) {
     const T* base = X + rc * K + G * PW + ab * 16 + 2 * (lane >> 4);
-    const d2v v0 = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(base));
-    const d2v v1 = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(base + 8));
+    d2v v0, v1;
+    if constexpr (NT) {
+      v0 = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(base));
+      v1 = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(base + 8));
+    } else {
+      v0 = *reinterpret_cast<const d2v*>(base);
+      v1 = *reinterpret_cast<const d2v*>(base + 8);
+    }
     a[0] = ok ? v0.x : 0.0;
     a[1] = ok ? v0.y : 0.0;
     a[2] = ok ? v1.x : 0.0;
     a[3] = ok ? v1.y : 0.0;
   } else {
-    const f4v v =
-        __builtin_nontemporal_load(reinterpret_cast<const f4v*>(X + rc * K + G * PW + ab * 16 + 4 * (lane >> 4)));
+    const f4v* src = reinterpret_cast<const f4v*>(X + rc * K + G * PW + ab * 16 + 4 * (lane >> 4));
+    f4v v;
+    if constexpr (NT)
+      v = __builtin_nontemporal_load(src);
+    else
+      v = *src;
     a[0] = ok ? static_cast<double>(v.x) : 0.0;
     a[1] = ok ? static_cast<double>(v.y) : 0.0;
     a[2] = ok ? static_cast<double>(v.z) : 0.0;
@@ -299,9 +317,30 @@ struct Lay;
 // the L2 and the 256 MB memory-side cache to what the next kernel reads: R
 // written by the R update, P written by the X/P pass, Q, and A. This is Q and R
 // in the R update, and X, the old P and R in the X/P pass (headline solve
-// 117.0 -> 109.0 ms).
+// 117.0 -> 108.2 ms). Two conditions:
+// - a wave's row slices cover whole 128-byte lines (the group spans the row,
+//   or its slice is a multiple of 128 bytes; stream_nt): a line shared with
+//   another wave's columns would be evicted before that wave reads its half
+//   (FP32, k = 64, 16-column groups: X/P pass 624 -> 915 us);
+// - the iteration's operands exceed the memory-side cache (Plan::nt): when
+//   they fit, everything stays cached anyway (FP32, 512^2, k = 32: 179 ->
+//   187 ms with non-temporal streams).
 template <>
 struct Lay<double> {
+  template <bool NT>
+  __device__ static void load_p(const double* p, double* v) {
+    if constexpr (NT)
+      load_nt(p, v);
+    else
+      load(p, v);
+  }
+  template <bool NT>
+  __device__ static void store_p(double* p, const double* v) {
+    if constexpr (NT)
+      store_nt(p, v);
+    else
+      store(p, v);
+  }
   __device__ static void load_nt(const double* p, double* v) {
     const d2v x = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
     v[0] = x.x;
@@ -323,6 +362,20 @@ struct Lay<double> {
 };
 template <>
 struct Lay<float> {
+  template <bool NT>
+  __device__ static void load_p(const float* p, float* v) {
+    if constexpr (NT)
+      load_nt(p, v);
+    else
+      load(p, v);
+  }
+  template <bool NT>
+  __device__ static void store_p(float* p, const float* v) {
+    if constexpr (NT)
+      store_nt(p, v);
+    else
+      store(p, v);
+  }
   __device__ static void load_nt(const float* p, float* v) {
     const f4v x = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
     v[0] = x.x;
@@ -459,7 +512,7 @@ constexpr int smem_doubles() {
 // the operands of the next tile are loaded before the products of the current
 // one (on the last tile of a wave the current tile is loaded again, from
 // cache); FP64 moves twice the bytes per product and gains nothing from it.
-template <typename T, int K, int PW>
+template <typename T, int K, int PW, bool NT>
 __global__ __launch_bounds__(kBlock) void k_update_r_mfma(Plan pl, T* __restrict__ R, const T* __restrict__ Q,
                                                           const T* __restrict__ lam, double* __restrict__ part,
                                                           const DevState* st) {
@@ -483,12 +536,12 @@ __global__ __launch_bounds__(kBlock) void k_update_r_mfma(Plan pl, T* __restrict
 #pragma unroll
     for (int m = 0; m < L::NR; ++m) {
       const int64_t row = min(t * 16 + L::row(m, lane), n - 1);
-      L::load_nt(R + row * K + cbase + jb * 16, r + m * L::NC);
+      L::template load_p<NT>(R + row * K + cbase + jb * 16, r + m * L::NC);
     }
   };
   auto load_tile = [&](int64_t t, double (&q)[NB][4], T (&r)[NB][4]) {
 #pragma unroll
-    for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW>(q[ab], Q, t * 16, n, G, ab, lane);
+    for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW, NT>(q[ab], Q, t * 16, n, G, ab, lane);
 #pragma unroll
     for (int jb = 0; jb < NB; ++jb) load_rows(t, jb, r[jb]);
   };
@@ -502,7 +555,7 @@ __global__ __launch_bounds__(kBlock) void k_update_r_mfma(Plan pl, T* __restrict
       load_tile(t + ww.stride < ww.end ? t + ww.stride : t, qn, rnx);
     } else {
 #pragma unroll
-      for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW>(qa[ab], Q, row0, n, G, ab, lane);
+      for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW, NT>(qa[ab], Q, row0, n, G, ab, lane);
     }
     double rn[NB][4];
 #pragma unroll
@@ -544,7 +597,7 @@ __global__ __launch_bounds__(kBlock) void k_update_r_mfma(Plan pl, T* __restrict
 // partial rho = <<P_new, R>> of the next iteration's line 6. FP32 with
 // single-block groups: operands of the next tile are loaded before the
 // products of the current one.
-template <typename T, int K, int PW>
+template <typename T, int K, int PW, bool NT>
 __global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restrict__ X, T* __restrict__ Pm,
                                                            const T* __restrict__ R, const T* __restrict__ lam,
                                                            const T* __restrict__ beta, double* __restrict__ part,
@@ -570,13 +623,13 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restric
 #pragma unroll
     for (int m = 0; m < L::NR; ++m) {
       const int64_t off = min(t * 16 + L::row(m, lane), n - 1) * K + cbase + jb * 16;
-      L::load_nt(X + off, x + m * L::NC);
-      if (!last) L::load_nt(R + off, r + m * L::NC);
+      L::template load_p<NT>(X + off, x + m * L::NC);
+      if (!last) L::template load_p<NT>(R + off, r + m * L::NC);
     }
   };
   auto load_tile = [&](int64_t t, double (&pq)[NB][4], T (&x)[NB][4], T (&r)[NB][4]) {
 #pragma unroll
-    for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW>(pq[ab], Pm, t * 16, n, G, ab, lane);
+    for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW, NT>(pq[ab], Pm, t * 16, n, G, ab, lane);
 #pragma unroll
     for (int jb = 0; jb < NB; ++jb) load_rows(t, jb, x[jb], r[jb]);
   };
@@ -590,7 +643,7 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restric
       load_tile(t + ww.stride < ww.end ? t + ww.stride : t, pnx, xnx, rnx);
     } else {
 #pragma unroll
-      for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW>(pa[ab], Pm, row0, n, G, ab, lane);
+      for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW, NT>(pa[ab], Pm, row0, n, G, ab, lane);
     }
     double pn[NB][4], rd[NB][4];
 #pragma unroll
@@ -618,7 +671,7 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restric
         T x[L::NC];
 #pragma unroll
         for (int e = 0; e < L::NC; ++e) x[e] = xa[jb][m * L::NC + e] + dx[m * L::NC + e];  // X + P lambda
-        if (ok) L::store_nt(X + off, x);
+        if (ok) L::template store_p<NT>(X + off, x);
         T* pvm = pv + m * L::NC;
         T* rvm = rv + m * L::NC;
 #pragma unroll
@@ -1155,6 +1208,10 @@ void mfma_sp_grid(Plan& pl) {
     const int64_t lim = int64_t(1) << 32;
     pl.sp_o32[prec] = pl.n * pl.k * elem < lim && pl.nnz * elem < lim && (pl.n + 1) * 4 < lim &&
                       !env_set("BCG_WIDE_OFFSETS");
+    // non-temporal streams in the update passes when X, R, P, Q and A
+    // together exceed the 256 MiB memory-side cache
+    const int64_t working = 4 * pl.n * pl.k * elem + pl.nnz * (elem + 4) + 4 * (pl.n + 1);
+    pl.nt[prec] = working > (int64_t(256) << 20);
   }
 }
 
@@ -1202,9 +1259,14 @@ template <typename T>
 void launch_update_r_mfma(const Plan& pl, T* R, const T* Q, const T* lam, double* part, const DevState* st,
                           hipStream_t s) {
   check_grid(pl, pl.mfma);
+  const bool nt = pl.nt[std::is_same<T, float>::value ? 1 : 0] != 0;
   dispatch_mfma(pl, [&](auto Kc, auto Wc) {
-    hipLaunchKernelGGL((k_update_r_mfma<T, decltype(Kc)::value, decltype(Wc)::value>), dim3(pl.nwg), dim3(kBlock), 0,
-                       s, pl, R, Q, lam, part, st);
+    constexpr int K = decltype(Kc)::value, W = decltype(Wc)::value;
+    if (stream_nt<T, K, W>() && nt)
+      hipLaunchKernelGGL((k_update_r_mfma<T, K, W, stream_nt<T, K, W>()>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, R,
+                         Q, lam, part, st);
+    else
+      hipLaunchKernelGGL((k_update_r_mfma<T, K, W, false>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, R, Q, lam, part, st);
   });
 }
 
@@ -1212,9 +1274,15 @@ template <typename T>
 void launch_update_xp_mfma(const Plan& pl, T* X, T* P, const T* R, const T* lam, const T* beta, double* part,
                            const DevState* st, hipStream_t s) {
   check_grid(pl, pl.mfma);
+  const bool nt = pl.nt[std::is_same<T, float>::value ? 1 : 0] != 0;
   dispatch_mfma(pl, [&](auto Kc, auto Wc) {
-    hipLaunchKernelGGL((k_update_xp_mfma<T, decltype(Kc)::value, decltype(Wc)::value>), dim3(pl.nwg), dim3(kBlock),
-                       0, s, pl, X, P, R, lam, beta, part, st);
+    constexpr int K = decltype(Kc)::value, W = decltype(Wc)::value;
+    if (stream_nt<T, K, W>() && nt)
+      hipLaunchKernelGGL((k_update_xp_mfma<T, K, W, stream_nt<T, K, W>()>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, X,
+                         P, R, lam, beta, part, st);
+    else
+      hipLaunchKernelGGL((k_update_xp_mfma<T, K, W, false>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, X, P, R, lam, beta,
+                         part, st);
   });
 }
 
