@@ -224,9 +224,25 @@ __global__ __launch_bounds__(kBlock) void k_residual(Plan pl, const int32_t* __r
     for (int e = tid; e < tr.ne; e += kBlock) {
       const int r = e / k, c = e - r * k;
       const int64_t i = tr.row0 + r;
+      // entries in chunks of 8: all index and value loads, then all gathers,
+      // then the products in entry order (an entry past the row end adds
+      // 0 * x for a clamped, valid column, which leaves s unchanged)
       double s = 0.0;
-      const int j1 = rowptr[i + 1];
-      for (int j = rowptr[i]; j < j1; ++j) s = fma(vals[j], X[(int64_t)colind[j] * k + c], s);
+      const int j0 = rowptr[i], j1 = rowptr[i + 1];
+      for (int jb = j0; jb < j1; jb += 8) {
+        int cols[8];
+        double vs[8], xs[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int jj = min(jb + u, j1 - 1);
+          cols[u] = colind[jj];
+          vs[u] = jb + u < j1 ? vals[jj] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xs[u] = X[(int64_t)cols[u] * k + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s = fma(vs[u], xs[u], s);
+      }
       const double v = B[tr.base + e] - s;
       R[tr.base + e] = v;
       if (with_p) P[tr.base + e] = v;
