@@ -783,7 +783,6 @@ __global__ __launch_bounds__(kBlock) void k_conv_beta(Plan pl, const double* __r
 // ---- one wave per p x p group (p in {2, 4, 8, 16, 32}), rows in registers ----
 // Lane i holds row i; the pivot row of each elimination step is broadcast
 // with readlane, so the factorisations need no LDS round trips or barriers.
-constexpr int kWaveP = 16;
 
 __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
