@@ -66,6 +66,35 @@ def _poisson_residual_ratios(N, B, X):
     return float(torch.max(torch.linalg.norm(R, dim=0) / torch.linalg.norm(B, dim=0)))
 
 
+@pytest.mark.timeout(600)
+def test_poisson3d_128_k16_headline_form():
+    """The benchmark's headline form exactly: 128^3 Poisson, k = 16, block,
+    tiled row order, FP32+refinement to 1e-8. The true residual is recomputed
+    with the plain PyTorch stencil; the solution must agree with the plain FP64
+    solve to the accuracy both reach (each is within 1e-8 of the exact
+    solution relative to the residual, so the solutions differ by about
+    kappa * 1e-8)."""
+    P = _P()
+    w = WORKLOADS["poisson3d_128_k16"]
+    log("128^3 k=16 block, FP32+refinement to 1e-8 (headline form)")
+    B = dev(rhs_for(w))
+    s = P.BCG(*P.stencil(w.dim, w.N), k=w.k, subalgebra="block")
+    s.set_row_schedule(P.stencil_schedule(w.dim, w.N, 32))
+    s.set_precision("fp32_refine")
+    X, info = s.solve(B, tol=w.tol)
+    log(f"status={info['status_name']} iterations={info['iterations']} outer={info['outer_iterations']} "
+        f"true_rel_res={info['true_rel_res']:.2e}")
+    assert info["status"] == oracle.OK and info["fp64_fallback"] == 0
+    ratio = _poisson_residual_ratios(w.N, B, X)
+    assert ratio <= w.tol * (1 + 1e-6)
+    assert abs(ratio - info["true_rel_res"]) <= 1e-3 * ratio
+    s.set_precision("fp64")
+    X64, i64 = s.solve(B, tol=w.tol)
+    assert i64["status"] == oracle.OK
+    assert _poisson_residual_ratios(w.N, B, X64) <= w.tol * (1 + 1e-6)
+    assert rel(host(X), host(X64)) <= 1e-6
+
+
 @pytest.mark.timeout(900)
 def test_poisson3d_256_k128_refinement_converges():
     P = _P()
