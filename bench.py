@@ -220,8 +220,9 @@ def main() -> int:
                     help="row order of the sparse product: 32x32 x-y tiles swept through z (3D), or natural")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (counter calibration)")
-    ap.add_argument("--study", default=None, choices=["repeat128"],
-                    help="repeat128: time to solve 128 right-hand sides in 128/k solves, k = 16..128, p = 16")
+    ap.add_argument("--study", default=None, choices=["repeat128", "gradient"],
+                    help="repeat128: time to solve 128 right-hand sides in 128/k solves, k = 16..128, p = 16; "
+                         "gradient: forward + adjoint backward of the 512^2 diffusion workload")
     ap.add_argument("--study-precisions", default="fp32_refine,fp64")
     ap.add_argument("--traffic-from", default=None,
                     help="write profiles/traffic.json from rocprofv3 --pmc databases in this folder")
@@ -231,11 +232,11 @@ def main() -> int:
     if args.traffic_from:
         return traffic_from(args.traffic_from, args.workload, args.variant)
 
-    if args.study == "repeat128":
+    if args.study:
         if args.gpus != 1:
             log("bench.py: only --gpus 1 is supported")
             return 2
-        return repeat_study(args)
+        return repeat_study(args) if args.study == "repeat128" else gradient_study(args)
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
@@ -430,6 +431,63 @@ def repeat_study(args) -> int:
             print(json.dumps(line), flush=True)
             del solver, X, batches
             torch.cuda.empty_cache()
+    return 0
+
+
+def gradient_study(args) -> int:
+    """Forward solve plus adjoint backward of the 512^2 diffusion workload
+    (k = 32, block): L = sum(W * X) with X = A(kappa)^{-1} B, gradients with
+    respect to B and to the cell coefficients kappa through the library's
+    autograd functions (assembly, solve, adjoint solve, sampled outer
+    product, coefficient VJP). One JSON line per precision: wall times of
+    the forward and the backward after one warm-up pass, medians of
+    `steps` passes."""
+    import torch
+
+    import paper_1912_11930_amd as P
+    from workload import WORKLOADS, cell_coefficients, loss_weights, rhs
+
+    w = WORKLOADS["diffusion2d_512_k32"]
+    dim, N, k = w.dim, w.N, w.k
+    dev = torch.device("cuda:0")
+    kappa0 = torch.tensor(cell_coefficients(dim, N, w.sigma), dtype=torch.float64, device=dev)
+    B = torch.from_numpy(rhs(w.n, k, w.rhs)).to(dev)
+    W = torch.from_numpy(loss_weights(w.n, k)).to(dev)
+    rp, ci, v0 = P.stencil(dim, N, kappa0)
+    tol = w.tol if args.tol is None else args.tol
+    for precision in args.study_precisions.split(","):
+        solver = P.BCG(rp, ci, v0, k=k, subalgebra="block")
+        solver.set_precision(precision)
+        fw, bw, its = [], [], None
+        for rep_i in range(args.warmup + max(args.steps, 1)):
+            kt = kappa0.clone().requires_grad_(True)
+            Bt = B.clone().requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            vals = P.StencilValues.apply(kt, dim, N)
+            X = P.BCGSolve.apply(vals, Bt, solver, tol, 100000)
+            loss = (W * X).sum()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            its_fwd = solver.info()["iterations"]
+            loss.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            its = (its_fwd, solver.info()["iterations"])
+            if rep_i >= args.warmup:
+                fw.append(t1 - t0)
+                bw.append(t2 - t1)
+        fw.sort()
+        bw.sort()
+        f_ms, b_ms = 1e3 * fw[len(fw) // 2], 1e3 * bw[len(bw) // 2]
+        line = {"study": "gradient", "workload": w.name, "variant": "block", "k": k, "precision": precision,
+                "tol": tol, "forward_ms": round(f_ms, 3), "backward_ms": round(b_ms, 3),
+                "total_ms": round(f_ms + b_ms, 3), "iterations_forward": its[0], "iterations_adjoint": its[1],
+                "grad_kappa_norm": float(torch.linalg.norm(kt.grad)), "grad_B_norm": float(torch.linalg.norm(Bt.grad)),
+                "passes": len(fw)}
+        print(json.dumps(line), flush=True)
+        del solver
+        torch.cuda.empty_cache()
     return 0
 
 
