@@ -218,9 +218,11 @@ def main() -> int:
                     help="preconditioner M of Algorithm 1 (jacobi: M = diag(A))")
     ap.add_argument("--schedule", default="tiled", choices=["tiled", "natural"],
                     help="row order of the sparse product: 32x32 x-y tiles swept through z (3D), or natural")
+    ap.add_argument("--sell", type=int, default=0, metavar="SIGMA",
+                    help="sparse product on SELL-16-SIGMA storage (SIGMA 1 or a multiple of 16; 0: CSR)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (counter calibration)")
-    ap.add_argument("--study", default=None, choices=["repeat128", "gradient"],
+    ap.add_argument("--study", default=None, choices=["repeat128", "gradient", "sell"],
                     help="repeat128: time to solve 128 right-hand sides in 128/k solves, k = 16..128, p = 16; "
                          "gradient: forward + adjoint backward of the 512^2 diffusion workload")
     ap.add_argument("--study-precisions", default="fp32_refine,fp64")
@@ -236,7 +238,8 @@ def main() -> int:
         if args.gpus != 1:
             log("bench.py: only --gpus 1 is supported")
             return 2
-        return repeat_study(args) if args.study == "repeat128" else gradient_study(args)
+        studies = {"repeat128": repeat_study, "gradient": gradient_study, "sell": sell_study}
+        return studies[args.study](args)
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
@@ -263,6 +266,9 @@ def main() -> int:
     if args.schedule == "tiled" and w.dim == 3:
         solver.set_row_schedule(P.stencil_schedule(w.dim, w.N, 32, device=dev))
         schedule = "tiled 32x32 (x,y) swept through z"
+    if args.sell:
+        solver.set_sell(True, args.sell)
+    matrix_format = f"sell-16-{args.sell}" if args.sell else "csr"
     p_eff = {"block": k, "parallel": 1}.get(args.variant, args.p or 1)
     torch.cuda.synchronize()
 
@@ -318,7 +324,8 @@ def main() -> int:
     dominant = head["dominant"]
     bytes_launch = algorithmic_bytes(dominant, n, nnz, k, args.precision)
     achieved = bytes_launch / (head["avg_ms"] * 1e-3) / 1e9
-    traffic = measured_traffic(dominant, w.name, args.variant, args.precision)
+    # the counter figures were taken with CSR storage
+    traffic = measured_traffic(dominant, w.name, args.variant, args.precision) if not args.sell else None
     info = head["info"]
 
     out = {
@@ -336,7 +343,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": w.name, "grid": f"{w.N}^{w.dim}", "n": n, "nnz": nnz, "k": k,
                    "variant": args.variant, "p": p_eff, "precision": args.precision, "tol": tol,
-                   "rhs": w.rhs, "row_schedule": schedule, "precond": args.precond},
+                   "rhs": w.rhs, "row_schedule": schedule, "precond": args.precond,
+                   "format": matrix_format},
         "iterations": head["iterations"],
         "outer_iterations": info["outer_iterations"] if info else None,
         "true_rel_res": info["true_rel_res"] if info else None,
@@ -488,6 +496,81 @@ def gradient_study(args) -> int:
         print(json.dumps(line), flush=True)
         del solver
         torch.cuda.empty_cache()
+    return 0
+
+
+def sell_study(args) -> int:
+    """CSR against SELL-16-sigma storage of the sparse product (sigma 1 and
+    256), k = 16, block, solves to 1e-8 in each precision, on two systems:
+    the 128^3 Poisson system in the tiled row order, and an irregular one,
+    the 2D 1024^2 diffusion system (sigma 0.5) plus symmetric couplings of
+    -0.05 between random far rows (3 pairs drawn per row) with the diagonal
+    raised by their row sums (rows of 4 to 27 entries, 11 on average). One JSON line per
+    system, format and precision: median wall time of `steps` solves after
+    `warmup`, and the sparse product's average launch time from one more
+    solve with events around that class only."""
+    import numpy as np
+    import scipy.sparse as sp
+    import torch
+
+    import paper_1912_11930_amd as P
+    from workload import WORKLOADS, cell_coefficients, long_range_pairs, rhs
+
+    dev = torch.device("cuda:0")
+    k = 16
+    w = WORKLOADS["poisson3d_128_k16"]
+    systems = [("poisson3d_128", P.stencil(3, 128, None, device=dev), P.stencil_schedule(3, 128, 32, device=dev))]
+    N = 1024
+    rp, ci, va = P.stencil(2, N, torch.from_numpy(cell_coefficients(2, N, 0.5)).to(dev), device=dev)
+    n = N * N
+    A = sp.csr_matrix((va.cpu().numpy(), ci.cpu().numpy(), rp.cpu().numpy()), shape=(n, n))
+    i, j = long_range_pairs(n, 3)
+    C = sp.coo_matrix((np.full(i.size, -0.05), (i, j)), shape=(n, n)).tocsr()
+    C = C + C.T
+    A = (A + C + sp.diags(np.asarray(abs(C).sum(axis=1)).ravel())).tocsr()
+    A.sort_indices()
+    systems.append(("longrange2d_1024", tuple(torch.from_numpy(x).to(dev) for x in
+                                              (A.indptr.astype(np.int32), A.indices.astype(np.int32),
+                                               A.data.astype(np.float64))), None))
+    for name, (rp, ci, va), order in systems:
+        n = rp.numel() - 1
+        lens = torch.diff(rp).cpu().numpy()
+        B = torch.from_numpy(rhs(n, k, "uniform")).to(dev)
+        for sigma in (0, 1, 256):
+            solver = P.BCG(rp, ci, va, k=k, subalgebra="block")
+            if order is not None:
+                solver.set_row_schedule(order)
+            if sigma:
+                solver.set_sell(True, sigma)
+            for precision in args.study_precisions.split(","):
+                solver.set_precision(precision)
+                X = torch.zeros_like(B)
+                times = []
+                for rep_i in range(args.warmup + max(args.steps, 1)):
+                    X.zero_()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    _, info = solver.solve(B, X, tol=1e-8, maxit=100000)
+                    torch.cuda.synchronize()
+                    if rep_i >= args.warmup:
+                        times.append(time.perf_counter() - t0)
+                solver.set_profiling(True, classes=["spmm"])
+                X.zero_()
+                solver.solve(B, X, tol=1e-8, maxit=100000)
+                launches, total_ms = solver.kernel_times()["spmm"]
+                solver.set_profiling(False)
+                times.sort()
+                ms = 1e3 * times[len(times) // 2]
+                line = {"study": "sell", "system": name, "n": n, "nnz": int(lens.sum()),
+                        "row_len_min_max": [int(lens.min()), int(lens.max())], "k": k, "variant": "block",
+                        "format": f"sell-16-{sigma}" if sigma else "csr", "precision": precision,
+                        "status": info["status_name"], "iterations": info["iterations"],
+                        "true_rel_res": info["true_rel_res"], "ms_per_solve": round(ms, 3),
+                        "rhs_solves_per_s": round(k / (ms / 1e3), 2),
+                        "spmm_avg_us": round(1e3 * total_ms / max(launches, 1), 2), "solves": len(times)}
+                print(json.dumps(line), flush=True)
+            del solver
+            torch.cuda.empty_cache()
     return 0
 
 

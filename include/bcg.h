@@ -201,6 +201,29 @@ int bcg_csr_outer(bcg_handle *h, const double *Y, const double *X, double alpha,
  */
 int bcg_set_row_schedule(bcg_handle *h, const int32_t *order);
 
+/*
+ * bcg_set_sell -- keep a SELL-C-sigma copy of the matrix (sliced ELLPACK,
+ * C = 16 rows per slice, rows sorted by decreasing length within windows of
+ * sigma consecutive rows; Section 4 names this format as the remedy for the
+ * sparse product's cache behaviour for wide blocks) and run the matrix-core
+ * sparse product on it. The rows are taken in the current row schedule
+ * (natural order without one); a later bcg_set_row_schedule rebuilds the
+ * copy. Every row of Q = A P is computed from the same entries in the same
+ * order as from CSR; with sigma = 1 the positions of the rows do not move,
+ * and a solve is bitwise the same as with CSR. Padding slots hold value 0 and
+ * the row's own column.
+ * enable: 1 builds (or rebuilds) the copy, 0 frees it. sigma: 1 (no
+ * sorting) or a multiple of 16. The layout is built on the host from a copy
+ * of the pattern; the values are taken from the handle's current values
+ * (after bcg_update_values and the Jacobi scaling) at the start of every
+ * solve. Solves whose row kernels are not the matrix-core ones (k not a
+ * multiple of 16, p outside the supported set, X not 16-byte aligned) use
+ * the CSR product. Storage: 4 (n/16 + 1) + 4 n + 20 s bytes for s padded
+ * slots. Errors: BCG_EINVAL for a bad sigma or more than 2^31 - 1 slots,
+ * BCG_ENOMEM, BCG_EHIP. Synchronous.
+ */
+int bcg_set_sell(bcg_handle *h, int enable, int sigma);
+
 /* Copies the summary of the last solve into *info (host struct). */
 int bcg_get_info(const bcg_handle *h, bcg_info *info);
 

@@ -68,6 +68,8 @@ struct Plan {
   int sp_o32[2];  // sparse product with 32-bit lane offsets (FP64, FP32)
   int nt[2];      // row kernels stream dead operands non-temporally (FP64, FP32)
   const int32_t* sched;  // processing order of the sparse-product rows (nullptr: natural)
+  int sell;     // 1: the matrix-core sparse product reads SELL-16-sigma storage
+                // (rowptr: slice starts, sched: position -> row)
 };
 
 Plan make_plan(int64_t n, int64_t nnz, int k, int p, int global, int dec);
@@ -134,6 +136,10 @@ void launch_axpy_scaled(int64_t count, double* X, const float* D, const double* 
 void launch_sampled_outer(int64_t n, int k, const int32_t* rowptr, const int32_t* colind, const double* Y,
                           const double* X, double alpha, double* out, hipStream_t s);
 void launch_cast_values(int64_t nnz, const double* v, float* v32, hipStream_t s);
+// values of SELL storage: slot e takes entry map[e] of v / v32 (0 where
+// map[e] < 0, the padding)
+void launch_sell_values(int64_t slots, const int32_t* map, const double* v, const float* v32, double* sv,
+                        float* sv32, hipStream_t s);
 void launch_check_range(const int32_t* order, int64_t n, int* flag, hipStream_t s);
 // k-specialised row kernels (16-byte aligned block vectors; see fast_supported)
 template <typename T>

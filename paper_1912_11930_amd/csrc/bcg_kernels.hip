@@ -1375,6 +1375,16 @@ __global__ __launch_bounds__(kBlock) void k_cast_values(int64_t nnz, const doubl
     v32[e] = static_cast<float>(v[e]);
 }
 
+__global__ __launch_bounds__(kBlock) void k_sell_values(int64_t slots, const int32_t* __restrict__ map,
+                                                        const double* __restrict__ v, const float* __restrict__ v32,
+                                                        double* __restrict__ sv, float* __restrict__ sv32) {
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < slots; e += (int64_t)gridDim.x * kBlock) {
+    const int32_t m = map[e];
+    sv[e] = m >= 0 ? v[m] : 0.0;
+    sv32[e] = m >= 0 ? v32[m] : 0.f;
+  }
+}
+
 // out[e] = alpha * <Y[row(e), :], X[col(e), :]>; L lanes per row.
 __global__ __launch_bounds__(kBlock) void k_sampled_outer(int64_t n, int k, int L, const int32_t* __restrict__ rowptr,
                                                           const int32_t* __restrict__ colind,
@@ -1683,6 +1693,13 @@ void launch_cast_values(int64_t nnz, const double* v, float* v32, hipStream_t s)
   const int64_t blocks = (nnz + kBlock - 1) / kBlock;
   const int grid = static_cast<int>(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096);
   hipLaunchKernelGGL(k_cast_values, dim3(grid), dim3(kBlock), 0, s, nnz, v, v32);
+}
+
+void launch_sell_values(int64_t slots, const int32_t* map, const double* v, const float* v32, double* sv,
+                        float* sv32, hipStream_t s) {
+  const int64_t blocks = (slots + kBlock - 1) / kBlock;
+  const int grid = static_cast<int>(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096);
+  hipLaunchKernelGGL(k_sell_values, dim3(grid), dim3(kBlock), 0, s, slots, map, v, v32, sv, sv32);
 }
 
 void launch_sampled_outer(int64_t n, int k, const int32_t* rowptr, const int32_t* colind, const double* Y,

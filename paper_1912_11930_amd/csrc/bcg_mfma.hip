@@ -735,6 +735,17 @@ __device__ __forceinline__ void st_at(E* base, EIdx<O32> e, const V& v) {
 // one step earlier), then the CSR range two steps ahead and the schedule
 // entry three steps ahead, and only then consumes the gathers. All loads are
 // unconditional (clamped rows and entries).
+//
+// SELL: the matrix is in sliced ELLPACK storage with slices of C = 16 step
+// positions (Section 4 names SELL-C-sigma as the remedy for the product's
+// cache behaviour). `rowptr` then holds the first slot of every slice, a
+// slice of width w stores its two halves of 8 positions one after the other,
+// each slot by slot: slot t of position 8 h + r of slice S sits at
+// rowptr[S] + 8 w h + 8 t + r in `colind` and `vals` (value 0 in padding),
+// and `pl.sched` maps positions to rows. A slice's width is the same for
+// every lane of a step, so the index loads are coalesced (an 8-row step
+// reads one contiguous run) and rows longer than 8 entries cost no
+// divergent chunk loop.
 __device__ __forceinline__ int dpp_ror8(int x) {
   return __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false);  // row_ror:8
 }
@@ -781,7 +792,7 @@ __device__ __forceinline__ void spread8(Row8<T>& r, int c, T v) {
   }
 }
 
-template <typename T, int K, int PW, bool O32>
+template <typename T, int K, int PW, bool O32, bool SELL>
 __global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __restrict__ rowptr,
                                                       const int32_t* __restrict__ colind, const T* __restrict__ vals,
                                                       const T* __restrict__ Pm, T* __restrict__ Q,
@@ -806,13 +817,34 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __
     e = e < n ? e : n - 1;
     return sched ? ld_at<O32, int32_t>(sched, static_cast<E>(e)) : static_cast<int>(e);
   };
-  // entry j0 + cg (clamped into the row; the value of an entry past j1 is 0,
-  // so its product adds nothing)
-  auto idx_load = [&](int j0, int j1, int& c, T& v) {
-    const int jj = max(min(j0 + cg, j1 - 1), 0);
-    c = ld_at<O32, int32_t>(colind, static_cast<E>(jj));
-    const T x = ld_at<O32, T>(vals, static_cast<E>(jj));
-    v = j0 + cg < j1 ? x : T(0);
+  // entry range of this lane's row for `step` (SELL: address of the row's
+  // slot 0 and the slice width; two steps of 8 positions share a slice)
+  auto range = [&](int64_t step, int row, int& j0, int& j1) {
+    if constexpr (SELL) {
+      const E sl = static_cast<E>(step >> 1);
+      const int b0 = ld_at<O32, int32_t>(rowptr, sl), b1 = ld_at<O32, int32_t>(rowptr, sl + 1);
+      j1 = (b1 - b0) >> 4;
+      j0 = b0 + 8 * j1 * static_cast<int>(step & 1) + rr;
+    } else {
+      j0 = ld_at<O32, int32_t>(rowptr, static_cast<E>(row));
+      j1 = ld_at<O32, int32_t>(rowptr, static_cast<E>(row) + 1);
+    }
+  };
+  // entry t0 + cg of the row (clamped into the row; the value of an entry
+  // past its end is 0, so its product adds nothing)
+  auto idx_load = [&](int j0, int j1, int t0, int& c, T& v) {
+    if constexpr (SELL) {
+      const int t = t0 + cg;
+      const int jj = j0 + 8 * min(t, j1 - 1);
+      c = ld_at<O32, int32_t>(colind, static_cast<E>(jj));
+      const T x = ld_at<O32, T>(vals, static_cast<E>(jj));
+      v = t < j1 ? x : T(0);
+    } else {
+      const int jj = max(min(j0 + t0 + cg, j1 - 1), 0);
+      c = ld_at<O32, int32_t>(colind, static_cast<E>(jj));
+      const T x = ld_at<O32, T>(vals, static_cast<E>(jj));
+      v = j0 + t0 + cg < j1 ? x : T(0);
+    }
   };
   const int64_t tw = ww.stride;
   const int64_t last = ww.end > ww.first ? ww.end - 1 : ww.first;
@@ -824,13 +856,11 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __
     cur_row = row_of(s);
     row1 = row_of(min(s + tw, last));
     row2 = row_of(min(s + 2 * tw, last));
-    cur.j0 = ld_at<O32, int32_t>(rowptr, static_cast<E>(cur_row));
-    cur.j1 = ld_at<O32, int32_t>(rowptr, static_cast<E>(cur_row) + 1);
-    nj0 = ld_at<O32, int32_t>(rowptr, static_cast<E>(row1));
-    nj1 = ld_at<O32, int32_t>(rowptr, static_cast<E>(row1) + 1);
+    range(s, cur_row, cur.j0, cur.j1);
+    range(min(s + tw, last), row1, nj0, nj1);
     int c;
     T v;
-    idx_load(cur.j0, cur.j1, c, v);
+    idx_load(cur.j0, cur.j1, 0, c, v);
     spread8<T>(cur, c, v);
   }
   for (; s < ww.end; s += tw) {
@@ -849,10 +879,9 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __
     nxt.j1 = nj1;
     int nc;
     T nv;
-    idx_load(nj0, nj1, nc, nv);
+    idx_load(nj0, nj1, 0, nc, nv);
     // 3. CSR range two steps ahead, schedule entry three steps ahead
-    nj0 = ld_at<O32, int32_t>(rowptr, static_cast<E>(row2));
-    nj1 = ld_at<O32, int32_t>(rowptr, static_cast<E>(row2) + 1);
+    range(min(s + 2 * tw, last), row2, nj0, nj1);
     const int row3 = row_of(min(s + 3 * tw, last));
     // 4. consume the gathers, block by block
     T q[NB][2];
@@ -873,11 +902,11 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma(Plan pl, const int32_t* __
       q[b][1] = q1;
     }
     // rows with more than 8 entries: remaining chunks without pipelining
-    for (int jb = cur.j0 + 8; jb < cur.j1; jb += 8) {
+    for (int t0 = 8; SELL ? t0 < cur.j1 : cur.j0 + t0 < cur.j1; t0 += 8) {
       Row8<T> ex;
       int c;
       T v;
-      idx_load(jb, cur.j1, c, v);
+      idx_load(cur.j0, cur.j1, t0, c, v);
       spread8<T>(ex, c, v);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
@@ -957,7 +986,7 @@ __device__ __forceinline__ void spread_quad(Row8f& r, const int (&c)[2], const f
   }
 }
 
-template <int K, int PW, bool O32>
+template <int K, int PW, bool O32, bool SELL>
 __global__ __launch_bounds__(kBlock) void k_spmm_mfma_f32(Plan pl, const int32_t* __restrict__ rowptr,
                                                           const int32_t* __restrict__ colind,
                                                           const float* __restrict__ vals, const float* __restrict__ Pm,
@@ -981,15 +1010,29 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma_f32(Plan pl, const int32_t
     e = e < n ? e : n - 1;
     return sched ? ld_at<O32, int32_t>(sched, static_cast<E>(e)) : static_cast<int>(e);
   };
-  // entries j0 + cq and j0 + cq + 4 (clamped into the row; past j1 the value
-  // is 0, so the product adds nothing)
-  auto idx_load = [&](int j0, int j1, int (&c)[2], float (&v)[2]) {
+  // entry range of this lane's row for `step` (SELL: address of the row's
+  // slot 0 and the slice width; one step per slice)
+  auto range = [&](int64_t step, int row, int& j0, int& j1) {
+    if constexpr (SELL) {
+      const int b0 = ld_at<O32, int32_t>(rowptr, static_cast<E>(step)),
+                b1 = ld_at<O32, int32_t>(rowptr, static_cast<E>(step) + 1);
+      j1 = (b1 - b0) >> 4;
+      j0 = b0 + 8 * j1 * (rr >> 3) + (rr & 7);
+    } else {
+      j0 = ld_at<O32, int32_t>(rowptr, static_cast<E>(row));
+      j1 = ld_at<O32, int32_t>(rowptr, static_cast<E>(row) + 1);
+    }
+  };
+  // entries t0 + cq and t0 + cq + 4 of the row (clamped into the row; past
+  // its end the value is 0, so the product adds nothing)
+  auto idx_load = [&](int j0, int j1, int t0, int (&c)[2], float (&v)[2]) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int jj = max(min(j0 + cq + 4 * h, j1 - 1), 0);
+      const int t = t0 + cq + 4 * h;
+      const int jj = SELL ? j0 + 8 * min(t, j1 - 1) : max(min(j0 + t, j1 - 1), 0);
       c[h] = ld_at<O32, int32_t>(colind, static_cast<E>(jj));
       const float x = ld_at<O32, float>(vals, static_cast<E>(jj));
-      v[h] = j0 + cq + 4 * h < j1 ? x : 0.f;
+      v[h] = (SELL ? t < j1 : j0 + t < j1) ? x : 0.f;
     }
   };
   const int64_t tw = ww.stride;
@@ -1002,13 +1045,11 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma_f32(Plan pl, const int32_t
     cur_row = row_of(s);
     row1 = row_of(min(s + tw, last));
     row2 = row_of(min(s + 2 * tw, last));
-    cur.j0 = ld_at<O32, int32_t>(rowptr, static_cast<E>(cur_row));
-    cur.j1 = ld_at<O32, int32_t>(rowptr, static_cast<E>(cur_row) + 1);
-    nj0 = ld_at<O32, int32_t>(rowptr, static_cast<E>(row1));
-    nj1 = ld_at<O32, int32_t>(rowptr, static_cast<E>(row1) + 1);
+    range(s, cur_row, cur.j0, cur.j1);
+    range(min(s + tw, last), row1, nj0, nj1);
     int c[2];
     float v[2];
-    idx_load(cur.j0, cur.j1, c, v);
+    idx_load(cur.j0, cur.j1, 0, c, v);
     spread_quad(cur, c, v);
   }
   for (; s < ww.end; s += tw) {
@@ -1033,9 +1074,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma_f32(Plan pl, const int32_t
     nxt.j1 = nj1;
     int nc[2];
     float nv[2];
-    idx_load(nj0, nj1, nc, nv);
-    nj0 = ld_at<O32, int32_t>(rowptr, static_cast<E>(row2));
-    nj1 = ld_at<O32, int32_t>(rowptr, static_cast<E>(row2) + 1);
+    idx_load(nj0, nj1, 0, nc, nv);
+    range(min(s + 2 * tw, last), row2, nj0, nj1);
     const int row3 = row_of(min(s + 3 * tw, last));
     float q[NB][4];
 #pragma unroll
@@ -1060,11 +1100,11 @@ __global__ __launch_bounds__(kBlock) void k_spmm_mfma_f32(Plan pl, const int32_t
 #pragma unroll
       for (int e = 0; e < 4; ++e) q[b][e] = a[e];
     }
-    for (int jb = cur.j0 + 8; jb < cur.j1; jb += 8) {
+    for (int t0 = 8; SELL ? t0 < cur.j1 : cur.j0 + t0 < cur.j1; t0 += 8) {
       Row8f ex;
       int c[2];
       float v[2];
-      idx_load(jb, cur.j1, c, v);
+      idx_load(cur.j0, cur.j1, t0, c, v);
       spread_quad(ex, c, v);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
@@ -1234,23 +1274,25 @@ void launch_spmm_mfma(const Plan& pl, const int32_t* rowptr, const int32_t* coli
   const int prec = std::is_same<T, float>::value ? 1 : 0;
   if (pl.sp_chunk[prec] == 0) check_grid(pl, pl.sp_w);
   const dim3 grid(pl.sp_nwg[prec]);
-  const bool o32 = pl.sp_o32[prec] != 0;
+  const int mode = (pl.sp_o32[prec] != 0 ? 1 : 0) | (pl.sell ? 2 : 0);
   dispatch_mfma_w(pl.k, pl.sp_w, [&](auto Kc, auto Wc) {
     constexpr int K = decltype(Kc)::value, W = decltype(Wc)::value;
-    if constexpr (std::is_same<T, float>::value) {
-      if (o32)
-        hipLaunchKernelGGL((k_spmm_mfma_f32<K, W, true>), grid, dim3(kBlock), 0, s, pl, rowptr, colind, vals, P, Q,
-                           part, st);
+    auto go = [&](auto O32c, auto SELLc) {
+      constexpr bool O32 = decltype(O32c)::value, SELL = decltype(SELLc)::value;
+      if constexpr (std::is_same<T, float>::value)
+        hipLaunchKernelGGL((k_spmm_mfma_f32<K, W, O32, SELL>), grid, dim3(kBlock), 0, s, pl, rowptr, colind, vals, P,
+                           Q, part, st);
       else
-        hipLaunchKernelGGL((k_spmm_mfma_f32<K, W, false>), grid, dim3(kBlock), 0, s, pl, rowptr, colind, vals, P, Q,
-                           part, st);
-    } else {
-      if (o32)
-        hipLaunchKernelGGL((k_spmm_mfma<T, K, W, true>), grid, dim3(kBlock), 0, s, pl, rowptr, colind, vals, P, Q,
-                           part, st);
-      else
-        hipLaunchKernelGGL((k_spmm_mfma<T, K, W, false>), grid, dim3(kBlock), 0, s, pl, rowptr, colind, vals, P, Q,
-                           part, st);
+        hipLaunchKernelGGL((k_spmm_mfma<T, K, W, O32, SELL>), grid, dim3(kBlock), 0, s, pl, rowptr, colind, vals, P,
+                           Q, part, st);
+    };
+    using t_ = std::true_type;
+    using f_ = std::false_type;
+    switch (mode) {
+      case 0: go(f_(), f_()); break;
+      case 1: go(t_(), f_()); break;
+      case 2: go(f_(), t_()); break;
+      default: go(t_(), t_()); break;
     }
   });
 }

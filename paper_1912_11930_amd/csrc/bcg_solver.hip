@@ -108,6 +108,13 @@ struct bcg_handle {
   float *lam32 = nullptr, *beta32 = nullptr;
   double *r0 = nullptr, *ratios = nullptr, *scale = nullptr;
   int32_t* sched = nullptr;  // optional row order of the sparse product
+  // SELL-16-sigma copy of the matrix for the matrix-core sparse product
+  int sell = 0, sell_sigma = 1;
+  int64_t sell_slots = 0;
+  int32_t *sl_ptr = nullptr, *sl_perm = nullptr, *sl_col = nullptr, *sl_map = nullptr;
+  double* sl_val = nullptr;
+  float* sl_val32 = nullptr;
+  Plan pl_sell{};  // pl with the SELL arrays' row order and offset widths
   DevState* st = nullptr;
   DevState* st_host = nullptr;  // pinned, 2 slots
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -146,7 +153,7 @@ void free_all(bcg_handle* h) {
   void* ptrs[] = {h->rowptr, h->colind, h->vals, h->vals32, h->R, h->P, h->Q, h->partA, h->part2, h->partR, h->partN,
                   h->alpha, h->rho, h->rnew, h->lam, h->beta, h->ws, h->lam32, h->beta32, h->r0, h->ratios,
                   h->scale, h->st, h->R32, h->P32, h->Q32, h->D32, h->sched, h->dscale, h->vals_s,
-                  h->vals32_s, h->Bs};
+                  h->vals32_s, h->Bs, h->sl_ptr, h->sl_perm, h->sl_col, h->sl_map, h->sl_val, h->sl_val32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->st_host) (void)hipHostFree(h->st_host);
@@ -241,7 +248,14 @@ void enqueue_iteration(bcg_handle* h, const IterBuffers<T>& b, double tol, int i
   hipStream_t s = h->stream;
   const bool mfma = h->path == RowPath::mfma, fast = mfma || h->path == RowPath::fast;
   timed(h, BCG_K_SPMM, it, [&] {  // lines 4-5
-    if (mfma)
+    if (mfma && h->sell) {
+      const T* sv;
+      if constexpr (std::is_same<T, float>::value)
+        sv = h->sl_val32;
+      else
+        sv = h->sl_val;
+      launch_spmm_mfma<T>(h->pl_sell, h->sl_ptr, h->sl_col, sv, b.P, b.Q, h->partA, h->st, s);
+    } else if (mfma)
       launch_spmm_mfma<T>(pl, h->rowptr, h->colind, b.vals, b.P, b.Q, h->partA, h->st, s);
     else if (fast)
       launch_spmm_fast<T>(pl, h->rowptr, h->colind, b.vals, b.P, b.Q, h->partA, h->st, s);
@@ -508,6 +522,106 @@ int solve_refine(bcg_handle* h, const double* B, double* X, double tol, int maxi
   }
 }
 
+void free_sell(bcg_handle* h) {
+  void* ptrs[] = {h->sl_ptr, h->sl_perm, h->sl_col, h->sl_map, h->sl_val, h->sl_val32};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  h->sl_ptr = h->sl_perm = h->sl_col = h->sl_map = nullptr;
+  h->sl_val = nullptr;
+  h->sl_val32 = nullptr;
+  h->sell_slots = 0;
+}
+
+// SELL-16-sigma layout of the handle's pattern, built on the host. Positions
+// follow the row schedule (natural order without one); within each window of
+// sigma positions the rows are sorted by decreasing length (stable). Slice S
+// holds positions 16 S .. 16 S + 15 (positions past n repeat the last row and
+// are masked by the kernels) and is as wide as its longest row (at least 1).
+// Its two halves of 8 positions follow each other, slot by slot: slot t of
+// position 8 h + r of slice S is entry ptr[S] + 8 w h + 8 t + r, the row's
+// t-th CSR entry, or padding (column = the row, map = -1, value 0).
+int build_sell(bcg_handle* h) {
+  const int64_t n = h->n, nnz = h->nnz;
+  std::vector<int32_t> rp(n + 1), ci(nnz > 0 ? nnz : 1), order(n);
+  HIP_TRY(hipMemcpy(rp.data(), h->rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+  if (nnz > 0) HIP_TRY(hipMemcpy(ci.data(), h->colind, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+  if (h->pl.sched)
+    HIP_TRY(hipMemcpy(order.data(), h->pl.sched, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  else
+    for (int64_t i = 0; i < n; ++i) order[i] = static_cast<int32_t>(i);
+  auto len = [&](int32_t r) { return rp[r + 1] - rp[r]; };
+  const int sigma = h->sell_sigma;
+  if (sigma > 1)
+    for (int64_t w0 = 0; w0 < n; w0 += sigma)
+      std::stable_sort(order.begin() + w0, order.begin() + std::min<int64_t>(n, w0 + sigma),
+                       [&](int32_t a, int32_t b) { return len(a) > len(b); });
+  const int64_t ns = (n + 15) / 16;
+  std::vector<int32_t> sp(ns + 1), perm(ns * 16), width(ns);
+  int64_t slots = 0;
+  for (int64_t S = 0; S < ns; ++S) {
+    int w = 1;
+    for (int r = 0; r < 16; ++r) {
+      const int64_t pos = 16 * S + r;
+      perm[pos] = order[pos < n ? pos : n - 1];
+      if (pos < n) w = std::max(w, len(perm[pos]));
+    }
+    width[S] = w;
+    sp[S] = static_cast<int32_t>(slots);
+    slots += 16 * static_cast<int64_t>(w);
+    if (slots > INT32_MAX) return fail(BCG_EINVAL, "SELL storage needs more than 2^31 - 1 slots");
+  }
+  sp[ns] = static_cast<int32_t>(slots);
+  std::vector<int32_t> col(slots), map(slots);
+  for (int64_t S = 0; S < ns; ++S)
+    for (int r = 0; r < 16; ++r) {
+      const int64_t pos = 16 * S + r;
+      const int32_t row = perm[pos];
+      const int l = pos < n ? len(row) : 0;
+      for (int t = 0; t < width[S]; ++t) {
+        const int64_t e = sp[S] + 8 * static_cast<int64_t>(width[S]) * (r >> 3) + 8 * t + (r & 7);
+        col[e] = t < l ? ci[rp[row] + t] : row;
+        map[e] = t < l ? rp[row] + t : -1;
+      }
+    }
+  int rc;
+  if ((rc = dalloc(&h->sl_ptr, ns + 1)) || (rc = dalloc(&h->sl_perm, ns * 16)) || (rc = dalloc(&h->sl_col, slots)) ||
+      (rc = dalloc(&h->sl_map, slots)) || (rc = dalloc(&h->sl_val, slots)) || (rc = dalloc(&h->sl_val32, slots)))
+    return rc;
+  HIP_TRY(hipMemcpy(h->sl_ptr, sp.data(), sizeof(int32_t) * (ns + 1), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->sl_perm, perm.data(), sizeof(int32_t) * ns * 16, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->sl_col, col.data(), sizeof(int32_t) * slots, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->sl_map, map.data(), sizeof(int32_t) * slots, hipMemcpyHostToDevice));
+  h->sell_slots = slots;
+  Plan& ps = h->pl_sell;
+  ps = h->pl;
+  ps.sched = h->sl_perm;
+  ps.sell = 1;
+  // 32-bit byte offsets when the vectors, the slots and the slice table all
+  // stay below 4 GiB (BCG_WIDE_OFFSETS forces 64-bit offsets)
+  const int64_t lim = int64_t(1) << 32;
+  const char* wide = std::getenv("BCG_WIDE_OFFSETS");
+  const bool force_wide = wide != nullptr && wide[0] != '\0' && wide[0] != '0';
+  for (int prec = 0; prec < 2; ++prec) {
+    const int64_t elem = prec ? 4 : 8;
+    ps.sp_o32[prec] = n * h->k * elem < lim && slots * elem < lim && ns * 16 * 4 < lim && !force_wide;
+  }
+  return BCG_OK;
+}
+
+// after a change of the row schedule: the SELL copy follows it
+int rebuild_sell(bcg_handle* h) {
+  if (!h->sell) return BCG_OK;
+  h->sell = 0;
+  free_sell(h);
+  const int rc = build_sell(h);
+  if (rc) {
+    free_sell(h);
+    return rc;
+  }
+  h->sell = 1;
+  return BCG_OK;
+}
+
 // Scale factors and scaled values of the Jacobi preconditioner for the
 // handle's current values. Synchronous (reads the flag).
 int jacobi_prepare(bcg_handle* h) {
@@ -683,6 +797,8 @@ int bcg_solve(bcg_handle* h, const double* B, double* X, double tol, int maxit) 
     std::swap(h->vals32, h->vals32_s);
     Bsolve = h->Bs;
   }
+  if (h->sell)
+    launch_sell_values(h->sell_slots, h->sl_map, h->vals, h->vals32, h->sl_val, h->sl_val32, h->stream);
   int rc = h->precision == BCG_FP32_REFINE ? solve_refine(h, Bsolve, X, tol, maxit)
                                            : solve_fp64(h, Bsolve, X, tol, maxit, nullptr, &its);
   if (jac) {
@@ -772,7 +888,7 @@ int bcg_set_row_schedule(bcg_handle* h, const int32_t* order) {
   HIP_TRY(hipStreamSynchronize(h->stream));
   if (!order) {
     h->pl.sched = nullptr;
-    return BCG_OK;
+    return rebuild_sell(h);
   }
   int rc;
   if (!h->sched && (rc = dalloc(&h->sched, h->n))) return rc;
@@ -789,6 +905,25 @@ int bcg_set_row_schedule(bcg_handle* h, const int32_t* order) {
     return fail(BCG_EINVAL, "row schedule has entries outside [0, n)");
   }
   h->pl.sched = h->sched;
+  return rebuild_sell(h);
+}
+
+int bcg_set_sell(bcg_handle* h, int enable, int sigma) {
+  if (!h) return fail(BCG_EINVAL, "handle is NULL");
+  if (enable && (sigma < 1 || (sigma > 1 && sigma % 16 != 0)))
+    return fail(BCG_EINVAL, "sigma must be 1 or a multiple of 16 (got %d)", sigma);
+  DeviceGuard g(h->device);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->sell = 0;
+  free_sell(h);
+  if (!enable) return BCG_OK;
+  h->sell_sigma = sigma;
+  const int rc = build_sell(h);
+  if (rc) {
+    free_sell(h);
+    return rc;
+  }
+  h->sell = 1;
   return BCG_OK;
 }
 

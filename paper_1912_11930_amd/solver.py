@@ -126,6 +126,16 @@ class BCG:
             check(self._lib.bcg_set_row_schedule(self._h, None if order is None else order.data_ptr()))
         self._sched = order
 
+    def set_sell(self, enable: bool = True, sigma: int = 1) -> None:
+        """Run the matrix-core sparse product on a SELL-16-sigma copy of A.
+
+        sigma: 1 (rows keep their positions) or a multiple of 16 (rows sorted
+        by decreasing length within windows of sigma positions).
+        """
+        with torch.cuda.device(self.device):
+            self._bind_stream()
+            check(self._lib.bcg_set_sell(self._h, int(bool(enable)), int(sigma)))
+
     def set_profiling(self, on: bool = True, classes=None) -> None:
         """Record HIP events around the launches of later solves.
 

@@ -58,5 +58,6 @@ def test_argument_validation_without_device(lib):
     assert lib.bcg_create(ctypes.byref(bad), 8, 0, 0, ctypes.byref(h)) == _capi.BCG_EINVAL
     assert lib.bcg_set_precision(None, 1, 1e-4, 10, 10) == _capi.BCG_EINVAL
     assert lib.bcg_solve(None, None, None, 1e-8, 10) == _capi.BCG_EINVAL
+    assert lib.bcg_set_sell(None, 1, 1) == _capi.BCG_EINVAL
     assert lib.bcg_stencil_build(4, 8, None, None, None, None, None) == _capi.BCG_EINVAL
     lib.bcg_destroy(None)
