@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import itertools
 import json
 import os
 import sys
@@ -501,7 +502,9 @@ def gradient_study(args) -> int:
 
 def sell_study(args) -> int:
     """CSR against SELL-16-sigma storage of the sparse product (sigma 1 and
-    256), k = 16, block, solves to 1e-8 in each precision, on two systems:
+    256), k = 16 (block) and k = 64 (hybrid, p = 16; the paper suggests the
+    format for the product's cache behaviour at larger k), solves to 1e-8 in
+    each precision, on two systems:
     the 128^3 Poisson system in the tiled row order, and an irregular one,
     the 2D 1024^2 diffusion system (sigma 0.5) plus symmetric couplings of
     -0.05 between random far rows (3 pairs drawn per row) with the diagonal
@@ -514,11 +517,9 @@ def sell_study(args) -> int:
     import torch
 
     import paper_1912_11930_amd as P
-    from workload import WORKLOADS, cell_coefficients, long_range_pairs, rhs
+    from workload import cell_coefficients, long_range_pairs, rhs
 
     dev = torch.device("cuda:0")
-    k = 16
-    w = WORKLOADS["poisson3d_128_k16"]
     systems = [("poisson3d_128", P.stencil(3, 128, None, device=dev), P.stencil_schedule(3, 128, 32, device=dev))]
     N = 1024
     rp, ci, va = P.stencil(2, N, torch.from_numpy(cell_coefficients(2, N, 0.5)).to(dev), device=dev)
@@ -532,12 +533,13 @@ def sell_study(args) -> int:
     systems.append(("longrange2d_1024", tuple(torch.from_numpy(x).to(dev) for x in
                                               (A.indptr.astype(np.int32), A.indices.astype(np.int32),
                                                A.data.astype(np.float64))), None))
-    for name, (rp, ci, va), order in systems:
+    for (name, (rp, ci, va), order), (k, variant, p) in itertools.product(systems, [(16, "block", 0),
+                                                                                    (64, "hybrid", 16)]):
         n = rp.numel() - 1
         lens = torch.diff(rp).cpu().numpy()
         B = torch.from_numpy(rhs(n, k, "uniform")).to(dev)
         for sigma in (0, 1, 256):
-            solver = P.BCG(rp, ci, va, k=k, subalgebra="block")
+            solver = P.BCG(rp, ci, va, k=k, subalgebra=variant, p=p)
             if order is not None:
                 solver.set_row_schedule(order)
             if sigma:
@@ -562,7 +564,8 @@ def sell_study(args) -> int:
                 times.sort()
                 ms = 1e3 * times[len(times) // 2]
                 line = {"study": "sell", "system": name, "n": n, "nnz": int(lens.sum()),
-                        "row_len_min_max": [int(lens.min()), int(lens.max())], "k": k, "variant": "block",
+                        "row_len_min_max": [int(lens.min()), int(lens.max())], "k": k, "variant": variant,
+                        "p": p or k,
                         "format": f"sell-16-{sigma}" if sigma else "csr", "precision": precision,
                         "status": info["status_name"], "iterations": info["iterations"],
                         "true_rel_res": info["true_rel_res"], "ms_per_solve": round(ms, 3),
