@@ -87,6 +87,33 @@ def test_sell_sigma1_bitwise_equals_csr(precision, name, k, variant, p):
     assert torch.equal(Xc, Xs)
 
 
+# every width and group instantiation of the two products: K = 64..128, groups
+# of 16, 32 and 64 columns, the global and parallel subalgebras
+KP_WIDE = [(64, "block", 0), (80, "hybrid", 8), (96, "parallel", 1), (112, "hybrid", 16), (128, "hybrid", 16),
+           (128, "global", 1)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+@pytest.mark.parametrize("k,variant,p", KP_WIDE)
+def test_sell_sigma1_bitwise_wide_blocks(precision, k, variant, p):
+    log(f"sell sigma=1 wide {precision} k={k} {variant} p={p}")
+    A = _matrix("long_range")
+    B = dev(rhs(A.shape[0], k, "normal", seed=700 + k))
+    csr, sell = _pair(A, k, variant, p, 1, precision)
+    if precision == "fp64":
+        Xc, ic = csr.solve(B, tol=0.0, maxit=6)
+        Xs, is_ = sell.solve(B, tol=0.0, maxit=6)
+    else:
+        Xc, ic = csr.solve(B, tol=1e-8)
+        Xs, is_ = sell.solve(B, tol=1e-8)
+        assert ic["status"] == is_["status"] == oracle.OK
+    assert ic["iterations"] == is_["iterations"]
+    assert torch.equal(Xc, Xs)
+    if precision == "fp64":
+        Xo, _ = oracle_solve(A, host(B), variant, p, tol=0.0, maxit=6)
+        assert rel(host(Xs), Xo) <= FIXED_TOL
+
+
 @pytest.mark.parametrize("sigma", [16, 64, 4096])
 @pytest.mark.parametrize("name", ["diffusion3d_13", "long_range"])
 @pytest.mark.parametrize("k,variant,p", [(16, "block", 0), (32, "hybrid", 8), (64, "hybrid", 8), (48, "global", 16)])
