@@ -224,6 +224,30 @@ int bcg_set_row_schedule(bcg_handle *h, const int32_t *order);
  */
 int bcg_set_sell(bcg_handle *h, int enable, int sigma);
 
+/*
+ * bcg_sell_layout -- the SELL-16-sigma layout that bcg_set_sell stores,
+ * computed from a CSR pattern on the host (no device work; for callers that
+ * inspect or reuse the layout, and for tests). All pointers are HOST arrays.
+ *   rowptr int32[n+1] (rowptr[0] = 0, non-decreasing), colind int32[rowptr[n]],
+ *   order int32[n] with entries in [0, n), or NULL for the natural order.
+ * Positions follow `order`; within each window of sigma positions the rows are
+ * sorted by decreasing length (stable). Slice S holds positions 16 S .. 16 S +
+ * 15 (positions past n repeat the last position's row) and has width w = the
+ * longest row length among its real positions, at least 1. Slot t of position
+ * 8 h + r of slice S (h in {0, 1}, r < 8) is entry
+ *   slice_ptr[S] + 8 w h + 8 t + r
+ * of col and map: the row's t-th CSR column and entry index, or for padding the
+ * row itself and -1.
+ * With slice_ptr NULL only the slot count is returned. Otherwise slice_ptr
+ * (ceil(n/16) + 1 entries), perm (16 ceil(n/16): position -> row), col and
+ * map (slot count entries each) are written.
+ * Returns the slot count, or BCG_EINVAL for a bad argument (sigma not 1 or a
+ * multiple of 16, a malformed rowptr, order out of range, more than 2^31 - 1
+ * slots).
+ */
+int64_t bcg_sell_layout(int64_t n, const int32_t *rowptr, const int32_t *colind, const int32_t *order, int sigma,
+                        int32_t *slice_ptr, int32_t *perm, int32_t *col, int32_t *map);
+
 /* Copies the summary of the last solve into *info (host struct). */
 int bcg_get_info(const bcg_handle *h, bcg_info *info);
 

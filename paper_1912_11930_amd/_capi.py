@@ -63,6 +63,9 @@ SIGNATURES = [
     ("bcg_get_column_ratios", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
     ("bcg_set_row_schedule", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("bcg_set_sell", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    ("bcg_sell_layout", ctypes.c_int64, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
     ("bcg_set_profiling", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("bcg_get_kernel_times", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KernelTime), ctypes.c_int]),
     ("bcg_last_error", ctypes.c_char_p, []),

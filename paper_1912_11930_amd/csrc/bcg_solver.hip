@@ -532,31 +532,28 @@ void free_sell(bcg_handle* h) {
   h->sell_slots = 0;
 }
 
-// SELL-16-sigma layout of the handle's pattern, built on the host. Positions
-// follow the row schedule (natural order without one); within each window of
-// sigma positions the rows are sorted by decreasing length (stable). Slice S
+// SELL-16-sigma layout of a CSR pattern, built on the host. Positions
+// follow `order_in` (natural order when NULL); within each window of sigma
+// positions the rows are sorted by decreasing length (stable). Slice S
 // holds positions 16 S .. 16 S + 15 (positions past n repeat the last row and
 // are masked by the kernels) and is as wide as its longest row (at least 1).
 // Its two halves of 8 positions follow each other, slot by slot: slot t of
 // position 8 h + r of slice S is entry ptr[S] + 8 w h + 8 t + r, the row's
 // t-th CSR entry, or padding (column = the row, map = -1, value 0).
-int build_sell(bcg_handle* h) {
-  const int64_t n = h->n, nnz = h->nnz;
-  std::vector<int32_t> rp(n + 1), ci(nnz > 0 ? nnz : 1), order(n);
-  HIP_TRY(hipMemcpy(rp.data(), h->rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
-  if (nnz > 0) HIP_TRY(hipMemcpy(ci.data(), h->colind, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
-  if (h->pl.sched)
-    HIP_TRY(hipMemcpy(order.data(), h->pl.sched, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
-  else
-    for (int64_t i = 0; i < n; ++i) order[i] = static_cast<int32_t>(i);
+int sell_layout_host(int64_t n, const int32_t* rp, const int32_t* ci, const int32_t* order_in, int sigma,
+                     std::vector<int32_t>& sp, std::vector<int32_t>& perm, std::vector<int32_t>& col,
+                     std::vector<int32_t>& map) {
+  std::vector<int32_t> order(n);
+  for (int64_t i = 0; i < n; ++i) order[i] = order_in ? order_in[i] : static_cast<int32_t>(i);
   auto len = [&](int32_t r) { return rp[r + 1] - rp[r]; };
-  const int sigma = h->sell_sigma;
   if (sigma > 1)
     for (int64_t w0 = 0; w0 < n; w0 += sigma)
       std::stable_sort(order.begin() + w0, order.begin() + std::min<int64_t>(n, w0 + sigma),
                        [&](int32_t a, int32_t b) { return len(a) > len(b); });
   const int64_t ns = (n + 15) / 16;
-  std::vector<int32_t> sp(ns + 1), perm(ns * 16), width(ns);
+  sp.assign(ns + 1, 0);
+  perm.assign(ns * 16, 0);
+  std::vector<int32_t> width(ns);
   int64_t slots = 0;
   for (int64_t S = 0; S < ns; ++S) {
     int w = 1;
@@ -571,7 +568,8 @@ int build_sell(bcg_handle* h) {
     if (slots > INT32_MAX) return fail(BCG_EINVAL, "SELL storage needs more than 2^31 - 1 slots");
   }
   sp[ns] = static_cast<int32_t>(slots);
-  std::vector<int32_t> col(slots), map(slots);
+  col.assign(slots, 0);
+  map.assign(slots, 0);
   for (int64_t S = 0; S < ns; ++S)
     for (int r = 0; r < 16; ++r) {
       const int64_t pos = 16 * S + r;
@@ -583,7 +581,25 @@ int build_sell(bcg_handle* h) {
         map[e] = t < l ? rp[row] + t : -1;
       }
     }
-  int rc;
+  return BCG_OK;
+}
+
+// The handle's SELL copy: the layout of its pattern in its row schedule,
+// uploaded, and the plan of the sparse product on it.
+int build_sell(bcg_handle* h) {
+  const int64_t n = h->n, nnz = h->nnz;
+  std::vector<int32_t> rp(n + 1), ci(nnz > 0 ? nnz : 1), order;
+  HIP_TRY(hipMemcpy(rp.data(), h->rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+  if (nnz > 0) HIP_TRY(hipMemcpy(ci.data(), h->colind, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+  if (h->pl.sched) {
+    order.resize(n);
+    HIP_TRY(hipMemcpy(order.data(), h->pl.sched, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  }
+  std::vector<int32_t> sp, perm, col, map;
+  int rc = sell_layout_host(n, rp.data(), ci.data(), h->pl.sched ? order.data() : nullptr, h->sell_sigma, sp, perm,
+                            col, map);
+  if (rc) return rc;
+  const int64_t ns = (n + 15) / 16, slots = sp[ns];
   if ((rc = dalloc(&h->sl_ptr, ns + 1)) || (rc = dalloc(&h->sl_perm, ns * 16)) || (rc = dalloc(&h->sl_col, slots)) ||
       (rc = dalloc(&h->sl_map, slots)) || (rc = dalloc(&h->sl_val, slots)) || (rc = dalloc(&h->sl_val32, slots)))
     return rc;
@@ -925,6 +941,32 @@ int bcg_set_sell(bcg_handle* h, int enable, int sigma) {
   }
   h->sell = 1;
   return BCG_OK;
+}
+
+int64_t bcg_sell_layout(int64_t n, const int32_t* rowptr, const int32_t* colind, const int32_t* order, int sigma,
+                        int32_t* slice_ptr, int32_t* perm, int32_t* col, int32_t* map) {
+  g_error.clear();
+  if (n < 1 || n >= INT32_MAX || !rowptr) return fail(BCG_EINVAL, "n must be in [1, 2^31 - 1) and rowptr non-NULL");
+  if (sigma < 1 || (sigma > 1 && sigma % 16 != 0))
+    return fail(BCG_EINVAL, "sigma must be 1 or a multiple of 16 (got %d)", sigma);
+  if (rowptr[0] != 0) return fail(BCG_EINVAL, "rowptr[0] must be 0");
+  for (int64_t i = 0; i < n; ++i)
+    if (rowptr[i + 1] < rowptr[i]) return fail(BCG_EINVAL, "rowptr decreases at row %lld", (long long)i);
+  if (rowptr[n] > 0 && !colind) return fail(BCG_EINVAL, "colind must be non-NULL");
+  if (order)
+    for (int64_t i = 0; i < n; ++i)
+      if (order[i] < 0 || order[i] >= n) return fail(BCG_EINVAL, "order has entries outside [0, n)");
+  std::vector<int32_t> sp, pm, cl, mp;
+  const int rc = sell_layout_host(n, rowptr, colind, order, sigma, sp, pm, cl, mp);
+  if (rc) return rc;
+  const int64_t ns = (n + 15) / 16, slots = sp[ns];
+  if (!slice_ptr) return slots;
+  if (!perm || !col || !map) return fail(BCG_EINVAL, "perm, col and map must be non-NULL with slice_ptr");
+  std::memcpy(slice_ptr, sp.data(), sizeof(int32_t) * (ns + 1));
+  std::memcpy(perm, pm.data(), sizeof(int32_t) * ns * 16);
+  std::memcpy(col, cl.data(), sizeof(int32_t) * slots);
+  std::memcpy(map, mp.data(), sizeof(int32_t) * slots);
+  return slots;
 }
 
 int bcg_get_info(const bcg_handle* h, bcg_info* info) {
