@@ -918,6 +918,7 @@ int bcg_set_row_schedule(bcg_handle* h, const int32_t* order) {
   if ((rc = read_state(h, &out))) return rc;
   if (out.status != 0) {
     h->pl.sched = nullptr;
+    (void)rebuild_sell(h);  // the SELL copy follows the natural order too
     return fail(BCG_EINVAL, "row schedule has entries outside [0, n)");
   }
   h->pl.sched = h->sched;

@@ -191,6 +191,22 @@ def test_sell_follows_values_schedule_and_jacobi():
     assert torch.equal(Xc, Xs)
 
 
+def test_sell_follows_rejected_schedule():
+    """A rejected row schedule leaves the natural order, for the SELL copy too."""
+    A = _matrix("diffusion2d_37")
+    B = dev(rhs(A.shape[0], 16, "normal", seed=12))
+    csr, sell = _pair(A, 16, "block", 0, 1)
+    order = torch.from_numpy(np.random.default_rng(4).permutation(A.shape[0]).astype(np.int32)).cuda()
+    sell.set_row_schedule(order)
+    bad = order.clone()
+    bad[5] = A.shape[0]
+    with pytest.raises(_P().BCGError):
+        sell.set_row_schedule(bad)
+    Xc, _ = csr.solve(B, tol=0.0, maxit=6)
+    Xs, _ = sell.solve(B, tol=0.0, maxit=6)
+    assert torch.equal(Xc, Xs)
+
+
 def test_sell_rejects_bad_sigma():
     P = _P()
     A = _matrix("diffusion2d_37")
