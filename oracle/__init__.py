@@ -18,8 +18,8 @@ vectorized Block Conjugate Gradients method"):
 * ``grad``    -- adjoint-solve gradient of a solve's output with respect to
   the matrix values and the cell coefficients.
 * ``refine``  -- FP32 inner solve with FP64 outer iterative refinement
-  (not in the paper; its iterates are "parity unpinned", only the final
-  FP64 accuracy is compared).
+  (not in the paper; its precision policy is pinned with exact rational
+  arithmetic).
 
 Status codes match the C ABI: OK 0, NOT_CONVERGED 1, EINVAL -1, EBREAKDOWN -2.
 """

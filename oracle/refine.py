@@ -1,9 +1,13 @@
 """FP32 inner block CG with FP64 outer iterative refinement -- oracle.
 
 TEST INFRASTRUCTURE ONLY. Not in the paper: this is the mixed-precision form
-of Algorithm 1 (Section 3, M = I). Its iterates depend on FP32 rounding order
-and are "parity unpinned"; what is compared with the GPU is the final FP64
-accuracy (true residual and distance to the FP64 solution).
+of Algorithm 1 (Section 3, M = I). Pinned on the CPU by
+tests/test_oracle_refine_policy.py: its block products against exact sums of
+FP32 operands, its coefficient rounding against exact rational updates, whole
+parallel inner iterations bit for bit against an exact-arithmetic simulation
+of the policy, and the distance of its FP32 iterates from the FP64 iteration
+(FP32 level). The GPU's inner iterates agree with it up to the rounding order
+of the FP32 sums; the final FP64 accuracy is compared as well.
 
 Inner solve (one restart per outer step, X starts at 0):
   matrix values, the sparse product and all n x k block vectors in FP32;

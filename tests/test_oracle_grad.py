@@ -3,8 +3,8 @@
 Gradient pins: a dense FP64 solve of the perturbed (possibly non-symmetric)
 system by finite differences, the dense outer-product formula, and finite
 differences of the stencil assembly. Mixed precision: the final FP64 true
-residual and the distance to a dense solve (its iterates are parity
-unpinned).
+residual and the distance to a dense solve (the precision policy of its inner
+iterations is pinned in tests/test_oracle_refine_policy.py).
 """
 import numpy as np
 import pytest

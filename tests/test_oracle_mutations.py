@@ -120,3 +120,54 @@ def test_jacobi_unmutated_passes():
         X, _ = ob.solve(A, B, v, p, tol=0.0, maxit=3, X0=X0, precond="jacobi")
         Xg = galerkin_iterate(A, B, X0, v, p, 3, minv=minv)
         assert np.linalg.norm(X - Xg) < 1e-9 * np.linalg.norm(Xg)
+
+
+# ---- precision policy of the refinement oracle (tests/test_oracle_refine_policy.py) ----
+import oracle.refine as orf  # noqa: E402
+from tests import test_oracle_refine_policy as pol  # noqa: E402
+
+
+def _apply32_unrounded(Y32, C64, p):
+    # the coefficients multiply the FP32 block without being rounded to FP32
+    n, k = Y32.shape
+    q = k // p
+    if p == 1:
+        c = C64[:, 0, 0]
+        return (Y32 * (c if c.shape[0] == k else c[0])).astype(np.float32)
+    out = np.empty_like(Y32)
+    for g in range(q):
+        Cg = C64[g] if C64.shape[0] == q else C64[0]
+        out[:, g * p:(g + 1) * p] = Y32[:, g * p:(g + 1) * p] @ Cg
+    return out
+
+
+def _product_fp32_accumulated(X32, Y32, variant, p):
+    # the block product summed in FP32, widened only at the end
+    return ob.block_product(X32, Y32, variant, p).astype(np.float64)
+
+
+def _policy_pins_fail():
+    fails = []
+    if pol.gram_pin_mismatches():
+        fails.append("gram")
+    if pol.apply_pin_mismatches():
+        fails.append("apply")
+    if pol.iteration_pin_mismatches():
+        fails.append("iterations")
+    return fails
+
+
+def test_refine_policy_unmutated_passes():
+    assert _policy_pins_fail() == []
+
+
+@pytest.mark.parametrize("mutation", ["coefficients_not_rounded", "gram_fp32_accumulated"])
+def test_refine_policy_mutation_is_caught(monkeypatch, mutation):
+    if mutation == "coefficients_not_rounded":
+        monkeypatch.setattr(orf, "_apply32", _apply32_unrounded)
+    else:
+        monkeypatch.setattr(orf, "_block_product64", _product_fp32_accumulated)
+    fails = _policy_pins_fail()
+    assert fails, mutation
+    # the whole-iteration pin catches both on its own
+    assert "iterations" in fails
