@@ -2,18 +2,25 @@
 
 A step is one complete solve A X = B from X = 0 to the stop rule (every
 column's residual reduced by 1e-8) of the synthetic 3D 7-point Poisson
-system on a 128^3 grid with k = 16 uniform right-hand sides, with every
-kernel of the iteration on the GPU and B, X, A resident in HBM before the
-timed region. value = k * steps / wall time.
+system on a 256^3 grid (n = 16,777,216) with k = 128 uniform right-hand
+sides, hybrid subalgebra with p = 16, in the FP32 + FP64-refinement form,
+with every kernel of the iteration on the GPU and B, X, A resident in HBM
+before the timed region. value = k * steps / wall time.
 
 Also reported on the same JSON line:
+  compare       the plain FP64 solve of the same system (its rate, the
+                speedup of the headline form, the difference of the two
+                solutions);
   roofline      the dominant kernel's algorithmic bytes per launch over its
                 event-measured average duration (events on the library's
                 stream, launches that returned at entry excluded);
   cpu_baseline  the FP64 CPU oracle on this host: a bounded number of its
-                iterations on the same full-size system, scaled to the
-                GPU's iteration count;
-  kernels       per-class time breakdown of one extra profiled solve.
+                iterations (on two sampled column groups for the hybrid
+                subalgebra, whose groups are independent block CG solves),
+                scaled to the whole solve;
+  kernels       per-class time breakdown of the last warm-up solve;
+  variants      the other subalgebras of the workload (one timed solve each
+                in both forms), when they fit the time budget.
 """
 from __future__ import annotations
 
@@ -165,6 +172,48 @@ def traffic_from(directory: str, workload: str, variant: str) -> int:
     return 0
 
 
+def cpu_baseline_groups(w, p: int, B_groups, gpu_iterations: int, budget_s: float):
+    """Hybrid subalgebra: its q = k/p column groups are independent block CG
+    solves of width p (Section 2), so the oracle times a bounded number of
+    block iterations on sampled groups of the full-size system and the solve
+    time is that per-group iteration time x q groups x the GPU's FP64
+    iteration count."""
+    from threadpoolctl import threadpool_info
+
+    from oracle.bcg import solve as oracle_solve
+    from oracle.stencil import stencil_csr
+    from workload import coefficients_for
+
+    A = stencil_csr(w.dim, w.N, coefficients_for(w))
+    q = w.k // p
+    t0 = time.perf_counter()
+    oracle_solve(A, B_groups[0][1], "block", p, tol=0.0, maxit=1)
+    t1 = time.perf_counter() - t0
+    m = max(2, min(gpu_iterations, int(budget_s / len(B_groups) / max(t1, 1e-3))))
+    total, its = 0.0, 0
+    for _, Bg in B_groups:
+        t0 = time.perf_counter()
+        oracle_solve(A, Bg, "block", p, tol=0.0, maxit=m)
+        total += time.perf_counter() - t0
+        its += m
+    per_it = total / its
+    t_solve = per_it * q * gpu_iterations
+    blas = [d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"]
+    cores = max(blas + [1])
+    groups = ", ".join(str(g) for g, _ in B_groups)
+    return {
+        "value": w.k / t_solve,
+        "unit": "RHS-solves/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"{m} block iterations (p={p}) of the FP64 NumPy/SciPy oracle on each of column groups "
+                   f"{groups} of the full {w.name} system ({total:.1f} s, {per_it * 1e3:.0f} ms per group "
+                   f"iteration), scaled to {q} groups x the GPU's {gpu_iterations} FP64 iterations; "
+                   f"sparse product single-threaded, BLAS on {cores} threads, host has {os.cpu_count()} "
+                   f"logical CPUs"),
+    }
+
+
 def cpu_baseline(w, variant: str, p: int, gpu_iterations: int, budget_s: float, precond: str = "none"):
     """Time the oracle's iterations on the full system; scale to the solve."""
     import numpy as np
@@ -204,11 +253,16 @@ def cpu_baseline(w, variant: str, p: int, gpu_iterations: int, budget_s: float, 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="poisson3d_128_k16")
-    ap.add_argument("--variant", default="block")
-    ap.add_argument("--p", type=int, default=0)
+    ap.add_argument("--workload", default="poisson3d_256_k128")
+    ap.add_argument("--variant", default="hybrid")
+    ap.add_argument("--p", type=int, default=16)
+    ap.add_argument("--compare-steps", type=int, default=1,
+                    help="timed solves of the other precision (after one profiled solve)")
+    ap.add_argument("--budget-s", type=float, default=420.0,
+                    help="wall-time budget (s) past which the optional variant solves are skipped")
+    ap.add_argument("--no-variants", action="store_true", help="skip the other subalgebras of the workload")
     ap.add_argument("--precision", default="fp32_refine", choices=["fp64", "fp32_refine"],
                     help="precision of the headline solve; the other form is timed beside it")
     ap.add_argument("--no-compare", action="store_true", help="skip the solve in the other precision")
@@ -253,41 +307,59 @@ def main() -> int:
     from paper_1912_11930_amd import _capi
     from workload import WORKLOADS, coefficients_for, rhs_for
 
+    t_start = time.perf_counter()
     w = WORKLOADS[args.workload]
     tol = w.tol if args.tol is None else args.tol
     dev = torch.device("cuda:0")
     kappa = coefficients_for(w)
     rp, ci, va = P.stencil(w.dim, w.N, None if kappa is None else torch.from_numpy(kappa).to(dev), device=dev)
-    B = torch.from_numpy(rhs_for(w)).to(dev)
     n, k, nnz = w.n, w.k, w.nnz
-    solver = P.BCG(rp, ci, va, k=k, subalgebra=args.variant, p=args.p)
-    if args.precond != "none":
-        solver.set_preconditioner(args.precond)
+    p_eff = {"block": k, "parallel": 1}.get(args.variant, args.p or 1)
+    B_host = rhs_for(w)
+    B = torch.from_numpy(B_host).to(dev)
+    # the oracle's sample (hybrid: the first and the last column group)
+    sample_groups = None
+    if not args.no_cpu_baseline and args.variant == "hybrid" and k // p_eff > 1:
+        q = k // p_eff
+        sample_groups = [(g, B_host[:, g * p_eff:(g + 1) * p_eff].copy()) for g in (0, q - 1)]
+    del B_host
+    order = None
     schedule = "natural"
     if args.schedule == "tiled" and w.dim == 3:
-        solver.set_row_schedule(P.stencil_schedule(w.dim, w.N, 32, device=dev))
+        order = P.stencil_schedule(w.dim, w.N, 32, device=dev)
         schedule = "tiled 32x32 (x,y) swept through z"
-    if args.sell:
-        solver.set_sell(True, args.sell)
+
+    def make_solver(variant: str, p: int):
+        sv = P.BCG(rp, ci, va, k=k, subalgebra=variant, p=p)
+        if args.precond != "none":
+            sv.set_preconditioner(args.precond)
+        if order is not None:
+            sv.set_row_schedule(order)
+        if args.sell:
+            sv.set_sell(True, args.sell)
+        return sv
+
+    solver = make_solver(args.variant, args.p)
     matrix_format = f"sell-16-{args.sell}" if args.sell else "csr"
-    p_eff = {"block": k, "parallel": 1}.get(args.variant, args.p or 1)
     torch.cuda.synchronize()
+    log(f"bench: set-up {time.perf_counter() - t_start:.1f} s")
 
     def run(precision: str, steps: int, warmup: int) -> dict:
-        """Warm-up solves, one more solve with every kernel class profiled (the
-        breakdown; after the warm-ups, so first-launch costs stay out of it),
-        then `steps` timed solves with events only around the dominant class."""
+        """Warm-up solves, the last of them with every kernel class profiled
+        (the breakdown; after the first warm-up, when there is one, so
+        first-launch costs stay out of it), then `steps` timed solves with
+        events only around the dominant class."""
         solver.set_precision(precision)
         X = torch.empty_like(B)
         log(f"bench: {w.name} n={n} nnz={nnz} k={k} variant={args.variant} p={p_eff} precision={precision}")
         info = None
-        for i in range(warmup + 1):
-            profiled = i == warmup
+        for i in range(max(warmup, 1)):
+            profiled = i == max(warmup, 1) - 1
             if profiled:
                 solver.set_profiling(True)
             X.zero_()
             _, info = solver.solve(B, X, tol=tol, maxit=100000)
-            log(f"{'profiled' if profiled else 'warmup'} {i}: status={info['status_name']} "
+            log(f"{'profiled warmup' if profiled else 'warmup'} {i}: status={info['status_name']} "
                 f"iterations={info['iterations']} {info['solve_ms']:.1f} ms true_rel_res={info['true_rel_res']:.2e}")
         breakdown = solver.kernel_times()
         solver.set_profiling(False)
@@ -359,24 +431,81 @@ def main() -> int:
     }
     if not args.no_compare:
         other = "fp64" if args.precision != "fp64" else "fp32_refine"
-        cmp_ = run(other, args.steps, 1)
+        cmp_ = run(other, args.compare_steps, 1)
         diff = float(torch.linalg.norm(head["X"] - cmp_["X"]) / torch.linalg.norm(cmp_["X"]))
+        cs = args.compare_steps
         out["compare"] = {
             "precision": other,
-            "value": k * args.steps / cmp_["elapsed"],
-            "ms_per_step": 1e3 * cmp_["elapsed"] / args.steps,
+            "value": k * cs / cmp_["elapsed"],
+            "ms_per_step": 1e3 * cmp_["elapsed"] / cs,
+            "steps": cs,
             "iterations": cmp_["iterations"],
             "true_rel_res": cmp_["info"]["true_rel_res"],
-            "speedup_of_headline": (k * args.steps / head["elapsed"]) / (k * args.steps / cmp_["elapsed"]),
+            "speedup_of_headline": (k * args.steps / head["elapsed"]) / (k * cs / cmp_["elapsed"]),
             "rel_diff_solutions": diff,
             "kernels": cmp_["kernels"],
         }
+        del cmp_
+    del head
     if not args.no_cpu_baseline:
         log("cpu_baseline: timing the oracle ...")
-        out["cpu_baseline"] = cpu_baseline(w, args.variant, p_eff, head_fp64_iterations(out), args.cpu_budget,
-                                           args.precond)
+        if sample_groups is not None:
+            out["cpu_baseline"] = cpu_baseline_groups(w, p_eff, sample_groups, head_fp64_iterations(out),
+                                                      args.cpu_budget)
+        else:
+            out["cpu_baseline"] = cpu_baseline(w, args.variant, p_eff, head_fp64_iterations(out), args.cpu_budget,
+                                               args.precond)
+        sample_groups = None
+    if not args.no_variants and w.variants:
+        solver.close()
+        torch.cuda.empty_cache()
+        out["variants"] = variant_solves(args, w, tol, B, make_solver, t_start, out)
+    log(f"bench: total {time.perf_counter() - t_start:.1f} s")
     print(json.dumps(out), flush=True)
     return 0
+
+
+def variant_solves(args, w, tol, B, make_solver, t_start: float, out: dict) -> list:
+    """One timed solve in each precision of every other subalgebra the
+    workload lists (after one untimed solve that also warms its kernels),
+    while the wall time stays inside the budget; a variant whose estimated
+    cost would overrun it is listed as skipped."""
+    import torch
+
+    res = []
+    head_p = {"block": w.k, "parallel": 1}.get(args.variant, args.p or 1)
+    per_rhs_s = out["ms_per_step"] / 1e3
+    for variant, p in w.variants:
+        if variant == args.variant and p == head_p:
+            continue
+        # a cost guess from the headline: the other forms iterate up to ~2x longer
+        need = 4 * 2.5 * per_rhs_s
+        if time.perf_counter() - t_start + need > args.budget_s:
+            res.append({"variant": variant, "p": p, "skipped": "time budget"})
+            continue
+        sv = make_solver(variant, p)
+        X = torch.empty_like(B)
+        rec = {"variant": variant, "p": p}
+        for precision in (args.precision, "fp64" if args.precision != "fp64" else "fp32_refine"):
+            sv.set_precision(precision)
+            X.zero_()
+            sv.solve(B, X, tol=tol, maxit=100000)
+            X.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = sv.solve(B, X, tol=tol, maxit=100000)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            log(f"variant {variant} p={p} {precision}: status={info['status_name']} "
+                f"iterations={info['iterations']} {1e3 * dt:.1f} ms")
+            rec[precision] = {"value": w.k / dt, "ms_per_step": 1e3 * dt, "iterations": info["iterations"],
+                              "outer_iterations": info["outer_iterations"], "status": info["status_name"],
+                              "true_rel_res": info["true_rel_res"]}
+        res.append(rec)
+        sv.close()
+        del X
+        torch.cuda.empty_cache()
+    return res
 
 
 def repeat_study(args) -> int:

@@ -107,8 +107,13 @@ typedef struct {
  *               GLOBAL p = 0 (means 1) or 1 <= p <= k with k % p == 0;
  *               HYBRID 1 <= p <= k with k % p == 0.
  *   out         host pointer receiving the new handle.
- * Returns BCG_EINVAL for invalid n, nnz, k, subalgebra or p (the CSR
- * contents are trusted: indices must be in range), BCG_ENOMEM, BCG_EHIP.
+ * Returns BCG_EINVAL for invalid n, nnz, k, subalgebra or p, and for
+ * malformed CSR contents: rowptr[0] != 0, a decreasing rowptr, rowptr[n] !=
+ * nnz, or a column index outside [0, n). The contents are checked on the
+ * device after the copy and before any kernel reads a row range, so a
+ * malformed matrix is rejected instead of driving a gather out of bounds.
+ * Symmetry and definiteness remain the caller's contract (a matrix without
+ * them can end a solve in BCG_EBREAKDOWN). BCG_ENOMEM, BCG_EHIP otherwise.
  * Section 2 (subalgebra definitions) fixes the admissible p.
  */
 int bcg_create(const bcg_csr *A, int k, int subalgebra, int p, bcg_handle **out);
@@ -195,9 +200,9 @@ int bcg_csr_outer(bcg_handle *h, const double *Y, const double *X, double alpha,
  * Section 4). order: device int32[n], a permutation of 0..n-1, copied.
  * Every row is computed exactly as before; only the order, and with it the
  * reuse of gathered rows of P in cache, changes (and the rounding order of
- * the partial alpha products). NULL restores the natural order. Entries
- * outside [0, n) return BCG_EINVAL; the permutation property itself is the
- * caller's contract. Synchronous.
+ * the partial alpha products). NULL restores the natural order. An order
+ * that is not a permutation (an entry outside [0, n), or a row listed twice)
+ * returns BCG_EINVAL and leaves the natural order. Synchronous.
  */
 int bcg_set_row_schedule(bcg_handle *h, const int32_t *order);
 

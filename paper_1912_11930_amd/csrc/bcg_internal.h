@@ -67,6 +67,7 @@ struct Plan {
   int sp_chunk[2];
   int sp_o32[2];  // sparse product with 32-bit lane offsets (FP64, FP32)
   int nt[2];      // row kernels stream dead operands non-temporally (FP64, FP32)
+  int ugw[2];     // column groups per wave of the matrix-core update passes (FP64, FP32)
   const int32_t* sched;  // processing order of the sparse-product rows (nullptr: natural)
   int sell;     // 1: the matrix-core sparse product reads SELL-16-sigma storage
                 // (rowptr: slice starts, sched: position -> row)
@@ -140,7 +141,9 @@ void launch_cast_values(int64_t nnz, const double* v, float* v32, hipStream_t s)
 // map[e] < 0, the padding)
 void launch_sell_values(int64_t slots, const int32_t* map, const double* v, const float* v32, double* sv,
                         float* sv32, hipStream_t s);
-void launch_check_range(const int32_t* order, int64_t n, int* flag, hipStream_t s);
+void launch_check_perm(const int32_t* order, int64_t n, int* seen, int* flag, hipStream_t s);
+void launch_check_csr(const int32_t* rowptr, const int32_t* colind, int64_t n, int64_t nnz, int* flag,
+                      hipStream_t s);
 // k-specialised row kernels (16-byte aligned block vectors; see fast_supported)
 template <typename T>
 void launch_spmm_fast(const Plan& pl, const int32_t* rowptr, const int32_t* colind, const T* vals, const T* P,

@@ -17,6 +17,7 @@
 // Block products <<X, Y>>_S (Section 2): the q diagonal p x p blocks
 // X_g^T Y_g of X^T Y (hybrid / block / parallel), or their sum (global), in
 // the packed layout [qo][p][p].
+#include <algorithm>
 #include <cfloat>
 #include <type_traits>
 #include <cmath>
@@ -1423,13 +1424,36 @@ void dispatch_shape(const Plan& pl, F&& f) {
   }
 }
 
-// flag = 1 if any order[e] is outside [0, n).
-__global__ __launch_bounds__(kBlock) void k_check_range(const int32_t* __restrict__ order, int64_t n,
-                                                        int* __restrict__ flag) {
+// flag = 1 if order is not a permutation of 0..n-1: an entry outside [0, n),
+// or a row taken twice (seen: n zeroed counters).
+__global__ __launch_bounds__(kBlock) void k_check_perm(const int32_t* __restrict__ order, int64_t n,
+                                                       int* __restrict__ seen, int* __restrict__ flag) {
   for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock) {
     const int32_t v = order[e];
-    if (v < 0 || v >= n) *reinterpret_cast<volatile int*>(flag) = 1;
+    if (v < 0 || v >= n || atomicAdd(seen + v, 1) != 0) *reinterpret_cast<volatile int*>(flag) = 1;
   }
+}
+
+// flag = 1 unless the CSR arrays describe n rows of nnz entries: rowptr[0] =
+// 0, rowptr non-decreasing, rowptr[n] = nnz, every column in [0, n). Only
+// rowptr[0..n] and colind[0..nnz) are read, so a malformed matrix is
+// rejected before any kernel follows its row ranges.
+__global__ __launch_bounds__(kBlock) void k_check_csr(const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ colind, int64_t n, int64_t nnz,
+                                                      int* __restrict__ flag) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i <= n; i += stride) {
+    const int32_t a = rowptr[i];
+    if (i == 0 && a != 0) bad = true;
+    if (i == n && a != nnz) bad = true;
+    if (i < n && rowptr[i + 1] < a) bad = true;
+  }
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nnz; e += stride) {
+    const int32_t c = colind[e];
+    if (c < 0 || c >= n) bad = true;
+  }
+  if (bad) *reinterpret_cast<volatile int*>(flag) = 1;
 }
 
 // Jacobi preconditioner M = diag(A): s_i = 1 / sqrt(a_ii) (duplicate
@@ -1505,10 +1529,17 @@ void launch_scale_rows(int64_t n, int k, const double* src, const double* dscale
   hipLaunchKernelGGL(k_scale_rows, dim3(grid), dim3(kBlock), 0, s, n, k, src, dscale, dst, divide);
 }
 
-void launch_check_range(const int32_t* order, int64_t n, int* flag, hipStream_t s) {
+void launch_check_perm(const int32_t* order, int64_t n, int* seen, int* flag, hipStream_t s) {
   const int64_t blocks = (n + kBlock - 1) / kBlock;
   const int grid = static_cast<int>(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096);
-  hipLaunchKernelGGL(k_check_range, dim3(grid), dim3(kBlock), 0, s, order, n, flag);
+  hipLaunchKernelGGL(k_check_perm, dim3(grid), dim3(kBlock), 0, s, order, n, seen, flag);
+}
+
+void launch_check_csr(const int32_t* rowptr, const int32_t* colind, int64_t n, int64_t nnz, int* flag,
+                      hipStream_t s) {
+  const int64_t m = std::max<int64_t>(n + 1, nnz), blocks = (m + kBlock - 1) / kBlock;
+  const int grid = static_cast<int>(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096);
+  hipLaunchKernelGGL(k_check_csr, dim3(grid), dim3(kBlock), 0, s, rowptr, colind, n, nnz, flag);
 }
 
 Plan make_plan(int64_t n, int64_t nnz, int k, int p, int global, int dec) {

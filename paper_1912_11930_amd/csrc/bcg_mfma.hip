@@ -42,9 +42,19 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 
 // Whether the row kernels may load an operand stream non-temporally: only
 // where a wave's row slices cover whole 128-byte lines (see Lay).
-template <typename T, int K, int PW>
+template <typename T, int K, int PW, int GW = 1>
 constexpr bool stream_nt() {
-  return K == PW || (PW * static_cast<int>(sizeof(T))) % 128 == 0;
+  return K == PW * GW || (PW * GW * static_cast<int>(sizeof(T))) % 128 == 0;
+}
+
+// Calls f(integral_constant<int, i>) for i = 0 .. N-1 (compile-time indices
+// into per-group register arrays).
+template <int N, int I = 0, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>());
+    static_for<N, I + 1>(f);
+  }
 }
 
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
@@ -186,7 +196,9 @@ template <typename T, int K, int PW, int NC>
 struct Coeff {
   using Gm = MGeo<K, PW>;
   static constexpr int NB = Gm::NB;
-  double r[NC][Gm::BREG ? NB * NB * 4 : 1];
+  // register copies in the coefficients' own precision (FP32 coefficients
+  // are FP32-rounded values, widened exactly at each use)
+  T r[NC][Gm::BREG ? NB * NB * 4 : 1];
   const double* lds;
 
   // Called by every thread of the workgroup.
@@ -202,7 +214,7 @@ struct Coeff {
           for (int jb = 0; jb < NB; ++jb)
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk)
-              r[c][(ab * NB + jb) * 4 + kk] = use[c] ? coeff_b<T, PW>(C[c], pl, G, ab, jb, kk, lane) : 0.0;
+              r[c][(ab * NB + jb) * 4 + kk] = use[c] ? static_cast<T>(coeff_b<T, PW>(C[c], pl, G, ab, jb, kk, lane)) : T(0);
     } else {
       static_assert(Gm::NG == 1, "LDS-staged coefficients need one group per workgroup");
       for (int c = 0; c < NC; ++c) {
@@ -218,39 +230,63 @@ struct Coeff {
   }
   __device__ __forceinline__ double b(int c, int ab, int jb, int kk, int lane) const {
     if constexpr (Gm::BREG) {
-      return r[c][(ab * NB + jb) * 4 + kk];
+      return static_cast<double>(r[c][(ab * NB + jb) * 4 + kk]);
     } else {
       return lds[c * PW * Gm::CST + coeff_row<T>(ab, kk, lane) * Gm::CST + jb * 16 + ord16<T>(lane & 15)];
     }
   }
 };
 
+// Value of lane l^8 (DPP row_ror:8 within each row of 16 lanes).
+__device__ __forceinline__ int xch(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float xch(float x) { return __int_as_float(xch(__float_as_int(x))); }
+__device__ __forceinline__ double xch(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = xch(static_cast<int>(v & 0xffffffffLL));
+  const int hi = xch(static_cast<int>(v >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
 // A operand of block ab: lane l holds row (l & 15) of the tile at the
 // columns coeff_row gives for k-steps kk = 0..3 (FP64: two 16-byte loads,
 // FP32: one). Rows past n read row n-1 and are zeroed. Non-temporal where
 // stream_nt allows: the operand (Q in the R update, the old P in the X/P
 // pass) is dead after it.
+//
+// FP64: each of the two loads covers whole 128-byte lines (8 rows x 16
+// doubles). Load h reads rows 8h .. 8h + 7: a lane whose bit 3 equals h reads
+// its own row's first pair (columns 2s, 2s + 1, s = l >> 4); the other lanes
+// read the second pair (columns 8 + 2s, 8 + 2s + 1) of the row of lane l ^ 8,
+// which one DPP swap between lanes l and l ^ 8 delivers. (Loading each
+// lane's own row twice covers only half of each line per instruction; with
+// non-temporal loads every half-line then costs its own DRAM access.)
 template <typename T, int K, int PW, bool NT>
 __device__ __forceinline__ void load_a(double (&a)[4], const T* __restrict__ X, int64_t row0, int64_t n, int G, int ab,
                                        int lane) {
   const int64_t r = row0 + (lane & 15);
   const bool ok = r < n;
-  const int64_t rc = ok ? r : n - 1;
   if constexpr (sizeof(T) == 8) {
-    const T* base = X + rc * K + G * PW + ab * 16 + 2 * (lane >> 4);
-    d2v v0, v1;
-    if constexpr (NT) {
-      v0 = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(base));
-      v1 = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(base + 8));
-    } else {
-      v0 = *reinterpret_cast<const d2v*>(base);
-      v1 = *reinterpret_cast<const d2v*>(base + 8);
+    const int s = lane >> 4, b3 = (lane >> 3) & 1;
+    d2v u[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t rh = min(row0 + (lane & 7) + 8 * h, n - 1);
+      const T* src = X + rh * K + G * PW + ab * 16 + (b3 == h ? 2 * s : 8 + 2 * s);
+      if constexpr (NT)
+        u[h] = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(src));
+      else
+        u[h] = *reinterpret_cast<const d2v*>(src);
     }
-    a[0] = ok ? v0.x : 0.0;
-    a[1] = ok ? v0.y : 0.0;
-    a[2] = ok ? v1.x : 0.0;
-    a[3] = ok ? v1.y : 0.0;
+    const d2v own = b3 ? u[1] : u[0], w = b3 ? u[0] : u[1];
+    const double o0 = xch(w.x), o1 = xch(w.y);
+    a[0] = ok ? own.x : 0.0;
+    a[1] = ok ? own.y : 0.0;
+    a[2] = ok ? o0 : 0.0;
+    a[3] = ok ? o1 : 0.0;
   } else {
+    const int64_t rc = ok ? r : n - 1;
     const f4v* src = reinterpret_cast<const f4v*>(X + rc * K + G * PW + ab * 16 + 4 * (lane >> 4));
     f4v v;
     if constexpr (NT)
@@ -264,16 +300,93 @@ __device__ __forceinline__ void load_a(double (&a)[4], const T* __restrict__ X, 
   }
 }
 
-// Value of lane l^8 (DPP row_ror:8 within each row of 16 lanes).
-__device__ __forceinline__ int xch(int x) {
-  return __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false);
+// Whole-line accesses of two adjacent 16-column FP32 groups (columns c0 ..
+// c0 + 31, one 128-byte line of each row) of a 16-row tile. Each of the two
+// instructions of an access covers 8 rows of both groups: 8 whole lines.
+// A lane's values of both groups stay in the layouts the products use; the
+// lane whose bit 3 differs from the instruction's index h moves the second
+// group's values of the row of lane l ^ 8 instead of its own, and one DPP
+// swap between lanes l and l ^ 8 delivers them. Addresses are the tile's
+// first row Mt (uniform) plus a 32-bit lane offset; rows past lim (the last
+// row below n, relative to the tile) read row lim and are not stored.
+template <bool NT>
+__device__ __forceinline__ f4v pair_ld(const float* Mt, int off) {
+  const f4v* src = reinterpret_cast<const f4v*>(reinterpret_cast<const char*>(Mt) + static_cast<uint32_t>(off) * 4u);
+  if constexpr (NT)
+    return __builtin_nontemporal_load(src);
+  else
+    return *src;
 }
-__device__ __forceinline__ float xch(float x) { return __int_as_float(xch(__float_as_int(x))); }
-__device__ __forceinline__ double xch(double x) {
-  const long long v = __double_as_longlong(x);
-  const int lo = xch(static_cast<int>(v & 0xffffffffLL));
-  const int hi = xch(static_cast<int>(v >> 32));
-  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+template <bool NT>
+__device__ __forceinline__ void pair_st(float* Mt, int off, f4v v) {
+  f4v* dst = reinterpret_cast<f4v*>(reinterpret_cast<char*>(Mt) + static_cast<uint32_t>(off) * 4u);
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, dst);
+  else
+    *dst = v;
+}
+
+// A operands: lane l holds row l & 15, columns 4s .. 4s + 3 (s = l >> 4) of
+// each group; rows past lim are zeroed.
+template <bool NT>
+__device__ __forceinline__ void pair_load_a(float (&a0)[4], float (&a1)[4], const float* Mt, int lim, int K, int c0,
+                                            int lane) {
+  const int b3 = (lane >> 3) & 1;
+  f4v u[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    u[h] = pair_ld<NT>(Mt, min((lane & 7) + 8 * h, lim) * K + c0 + (b3 == h ? 0 : 16) + 4 * (lane >> 4));
+  const f4v own = b3 ? u[1] : u[0], w = b3 ? u[0] : u[1];
+  const bool ok = (lane & 15) <= lim;
+  const float o[4] = {xch(w.x), xch(w.y), xch(w.z), xch(w.w)};
+  const float m[4] = {own.x, own.y, own.z, own.w};
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    a0[e] = ok ? m[e] : 0.0f;
+    a1[e] = ok ? o[e] : 0.0f;
+  }
+}
+
+// Row-layout values (the FP32 quad layout of the updates: lane l holds row
+// 4t + s, t = (l >> 2) & 3, s = l >> 4, columns 4c .. 4c + 3, c = l & 3, of
+// each group). Instruction h moves rows 8h .. 8h + 7 (t = 2h, 2h + 1).
+__device__ __forceinline__ int pair_row(int h, int lane) { return 4 * (2 * h + ((lane >> 2) & 1)) + (lane >> 4); }
+template <bool NT>
+__device__ __forceinline__ void pair_load(float (&g0)[4], float (&g1)[4], const float* Mt, int lim, int K, int c0,
+                                          int lane) {
+  const int b3 = (lane >> 3) & 1;
+  f4v u[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    u[h] = pair_ld<NT>(Mt, min(pair_row(h, lane), lim) * K + c0 + (b3 == h ? 0 : 16) + 4 * (lane & 3));
+  const f4v own = b3 ? u[1] : u[0], w = b3 ? u[0] : u[1];
+  g0[0] = own.x;
+  g0[1] = own.y;
+  g0[2] = own.z;
+  g0[3] = own.w;
+  g1[0] = xch(w.x);
+  g1[1] = xch(w.y);
+  g1[2] = xch(w.z);
+  g1[3] = xch(w.w);
+}
+// Stores the rows up to lim (values in the quad layout of both groups).
+template <bool NT>
+__device__ __forceinline__ void pair_store(float* Mt, const float (&g0)[4], const float (&g1)[4], int lim, int K,
+                                           int c0, int lane) {
+  const int b3 = (lane >> 3) & 1;
+  const f4v own = {g0[0], g0[1], g0[2], g0[3]};
+  const f4v w = {xch(g1[0]), xch(g1[1]), xch(g1[2]), xch(g1[3])};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = pair_row(h, lane);
+    if (r <= lim) pair_st<NT>(Mt, r * K + c0 + (b3 == h ? 0 : 16) + 4 * (lane & 3), b3 == h ? own : w);
+  }
+}
+
+// Last row below n of the tile starting at row0, relative to it (0..15).
+__device__ __forceinline__ int tile_lim(int64_t row0, int64_t n) {
+  const int64_t l = n - 1 - row0;
+  return l < 15 ? static_cast<int>(l) : 15;
 }
 
 // 4 x 4 transpose among lanes l, l^4, l^8, l^12 (t = (l>>2)&3): in v[e] =
@@ -457,8 +570,8 @@ __device__ __forceinline__ void gram_tiles(MAcc<NB>& acc, const double (&x)[NB][
 // the product <<R, R>>). The tiles hold rows and columns in sigma order within
 // each 16-column block (tau order for the FP32 sparse product). H: HS + K
 // doubles of LDS.
-template <int K, int PW, bool NORMS, Perm PM = Perm::sigma>
-__device__ void finish_mfma(MAcc<PW / 16>& acc, int G, double* H, double* prow, const Plan& pl) {
+template <int K, int PW, bool NORMS, Perm PM = Perm::sigma, int GW = 1>
+__device__ void finish_mfma(MAcc<PW / 16> (&acc)[GW], int G0, double* H, double* prow, const Plan& pl) {
   using Gm = MGeo<K, PW>;
   constexpr int NB = Gm::NB, HS = Gm::HS;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -467,17 +580,20 @@ __device__ void finish_mfma(MAcc<PW / 16>& acc, int G, double* H, double* prow, 
   __syncthreads();
   for (int w = 0; w < 4; ++w) {
     if (wave == w) {
-      double* HG = H + G * PW * PW;
 #pragma unroll
-      for (int ab = 0; ab < NB; ++ab)
+      for (int g = 0; g < GW; ++g) {
+        double* HG = H + (G0 + g) * PW * PW;
 #pragma unroll
-        for (int jb = 0; jb < NB; ++jb)
+        for (int ab = 0; ab < NB; ++ab)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int ti = PM == Perm::sigma ? sigma16(4 * r + (lane >> 4)) : tau16(4 * r + (lane >> 4));
-            const int tj = PM == Perm::sigma ? sigma16(lane & 15) : tau16(lane & 15);
-            HG[(ab * 16 + ti) * PW + jb * 16 + tj] += acc.g[ab * NB + jb][r];
-          }
+          for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int ti = PM == Perm::sigma ? sigma16(4 * r + (lane >> 4)) : tau16(4 * r + (lane >> 4));
+              const int tj = PM == Perm::sigma ? sigma16(lane & 15) : tau16(lane & 15);
+              HG[(ab * 16 + ti) * PW + jb * 16 + tj] += acc[g].g[ab * NB + jb][r];
+            }
+      }
     }
     __syncthreads();
   }
@@ -499,6 +615,12 @@ __device__ void finish_mfma(MAcc<PW / 16>& acc, int G, double* H, double* prow, 
     }
 }
 
+template <int K, int PW, bool NORMS, Perm PM = Perm::sigma>
+__device__ __forceinline__ void finish_mfma(MAcc<PW / 16>& acc, int G, double* H, double* prow, const Plan& pl) {
+  MAcc<PW / 16> one[1] = {acc};
+  finish_mfma<K, PW, NORMS, PM, 1>(one, G, H, prow, pl);
+}
+
 template <int K, int PW, int NC>
 constexpr int smem_doubles() {
   using Gm = MGeo<K, PW>;
@@ -508,11 +630,16 @@ constexpr int smem_doubles() {
 
 // ------------------------------------------------------------ R update
 // R -= Q lambda (line 9) and the partial <<R, R>> (line 11), whose diagonal
-// gives the column norms of the stop rule. FP32 with single-block groups:
-// the operands of the next tile are loaded before the products of the current
-// one (on the last tile of a wave the current tile is loaded again, from
-// cache); FP64 moves twice the bytes per product and gains nothing from it.
-template <typename T, int K, int PW, bool NT>
+// gives the column norms of the stop rule. A wave takes GW adjacent column
+// groups of each of its tiles, one after the other: with GW PW-column groups
+// covering a whole 128-byte line of every row, no line is shared with
+// another wave and the streams may be non-temporal (FP32, 16-column groups:
+// GW = 2). FP32 with single-block groups: the operands of the next unit (a
+// tile's next group, or the next tile's first) are loaded before the products
+// of the current one (on the last tile of a wave the current tile is loaded
+// again, from cache); FP64 moves twice the bytes per product and gains
+// nothing from it.
+template <typename T, int K, int PW, bool NT, int GW>
 __global__ __launch_bounds__(kBlock) void k_update_r_mfma(Plan pl, T* __restrict__ R, const T* __restrict__ Q,
                                                           const T* __restrict__ lam, double* __restrict__ part,
                                                           const DevState* st) {
@@ -520,84 +647,135 @@ __global__ __launch_bounds__(kBlock) void k_update_r_mfma(Plan pl, T* __restrict
   using Gm = MGeo<K, PW>;
   using L = Lay<T>;
   constexpr int NB = Gm::NB;
+  static_assert(Gm::NG % GW == 0 && (GW == 1 || Gm::BREG), "groups per wave");
   __shared__ double smem[smem_doubles<K, PW, 1>()];
   const int lane = threadIdx.x & 63;
   const int64_t n = pl.n;
-  const WaveWork ww = wave_work<Gm::NG>((n + 15) / 16);
-  const int G = ww.group;
-  const int cbase = G * PW + L::col(lane);
-  Coeff<T, K, PW, 1> cf;
-  cf.load({lam}, {true}, pl, G, smem);
-  MAcc<NB> acc;
-  acc.zero();
+  const WaveWork ww = wave_work<Gm::NG / GW>((n + 15) / 16);
+  const int G0 = ww.group * GW;
+  Coeff<T, K, PW, 1> cf[GW];
+#pragma unroll
+  for (int g = 0; g < GW; ++g) cf[g].load({lam}, {true}, pl, G0 + g, smem);
+  MAcc<NB> acc[GW];
+#pragma unroll
+  for (int g = 0; g < GW; ++g) acc[g].zero();
   double qa[NB][4];
   T ra[NB][4];
-  auto load_rows = [&](int64_t t, int jb, T (&r)[4]) {
+  auto load_rows = [&](int64_t t, int G, int jb, T (&r)[4]) {
+    const int cbase = G * PW + L::col(lane);
 #pragma unroll
     for (int m = 0; m < L::NR; ++m) {
       const int64_t row = min(t * 16 + L::row(m, lane), n - 1);
       L::template load_p<NT>(R + row * K + cbase + jb * 16, r + m * L::NC);
     }
   };
-  auto load_tile = [&](int64_t t, double (&q)[NB][4], T (&r)[NB][4]) {
+  auto load_unit = [&](int64_t t, int G, double (&q)[NB][4], T (&r)[NB][4]) {
 #pragma unroll
     for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW, NT>(q[ab], Q, t * 16, n, G, ab, lane);
 #pragma unroll
-    for (int jb = 0; jb < NB; ++jb) load_rows(t, jb, r[jb]);
+    for (int jb = 0; jb < NB; ++jb) load_rows(t, G, jb, r[jb]);
   };
   constexpr bool PIPE = sizeof(T) == 4 && NB == 1;
-  if (PIPE && ww.first < ww.end) load_tile(ww.first, qa, ra);
-  for (int64_t t = ww.first; t < ww.end; t += ww.stride) {
-    const int64_t row0 = t * 16;
-    double qn[NB][4];
-    T rnx[NB][4];
-    if constexpr (PIPE) {
-      load_tile(t + ww.stride < ww.end ? t + ww.stride : t, qn, rnx);
-    } else {
+  if constexpr (sizeof(T) == 4 && GW == 2 && NB == 1) {
+    // both groups of a tile at once, every access a whole line of each row
+    const int c0 = G0 * PW;
+    float q2[2][4], r2[2][4];
+    auto load_pair = [&](int64_t t, float (&q)[2][4], float (&r)[2][4]) {
+      const int lim = tile_lim(t * 16, n);
+      pair_load_a<NT>(q[0], q[1], Q + t * 16 * K, lim, K, c0, lane);
+      pair_load<NT>(r[0], r[1], R + t * 16 * K, lim, K, c0, lane);
+    };
+    if (ww.first < ww.end) load_pair(ww.first, q2, r2);
+    for (int64_t t = ww.first; t < ww.end; t += ww.stride) {
+      const int64_t row0 = t * 16;
+      float qn[2][4], rnx[2][4];
+      load_pair(t + ww.stride < ww.end ? t + ww.stride : t, qn, rnx);
+      const bool ok = row0 + L::row(0, lane) < n;
+      float rv[2][4];
+      double rn[2][1][4];
 #pragma unroll
-      for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW, NT>(qa[ab], Q, row0, n, G, ab, lane);
-    }
-    double rn[NB][4];
+      for (int g = 0; g < 2; ++g) {
+        d4 D = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int jb = 0; jb < NB; ++jb) {
-      d4 D = {0.0, 0.0, 0.0, 0.0};
+        for (int kk = 0; kk < 4; ++kk) D = mfma(static_cast<double>(q2[g][kk]), cf[g].b(0, 0, 0, kk, lane), D);
+        float dq[4];
+        to_rows(D, dq, lane);
 #pragma unroll
-      for (int ab = 0; ab < NB; ++ab)
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) D = mfma(qa[ab][kk], cf.b(0, ab, jb, kk, lane), D);
-      if constexpr (!PIPE) load_rows(t, jb, ra[jb]);
-      T dq[4], rv[4];
-      to_rows(D, dq, lane);
-#pragma unroll
-      for (int m = 0; m < L::NR; ++m) {
-        const int64_t row = row0 + L::row(m, lane);
-        const bool ok = row < n;
-        T* v = rv + m * L::NC;
-#pragma unroll
-        for (int e = 0; e < L::NC; ++e) v[e] = ok ? ra[jb][m * L::NC + e] - dq[m * L::NC + e] : T(0);  // R - Q lambda
-        if (ok) L::store(R + row * K + cbase + jb * 16, v);
+        for (int e = 0; e < 4; ++e) rv[g][e] = ok ? r2[g][e] - dq[e] : 0.0f;  // R - Q lambda
+        from_rows(rv[g], rn[g][0], lane);
       }
-      from_rows(rv, rn[jb], lane);
-    }
-    gram_tiles<NB>(acc, rn, rn);
-    if constexpr (PIPE)
+      pair_store<false>(R + row0 * K, rv[0], rv[1], tile_lim(row0, n), K, c0, lane);
 #pragma unroll
-      for (int jb = 0; jb < NB; ++jb)
+      for (int g = 0; g < 2; ++g) gram_tiles<1>(acc[g], rn[g], rn[g]);
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          qa[jb][e] = qn[jb][e];
-          ra[jb][e] = rnx[jb][e];
+          q2[g][e] = qn[g][e];
+          r2[g][e] = rnx[g][e];
         }
+    }
+  } else {
+  if (PIPE && ww.first < ww.end) load_unit(ww.first, G0, qa, ra);
+  for (int64_t t = ww.first; t < ww.end; t += ww.stride) {
+    const int64_t row0 = t * 16;
+    static_for<GW>([&](auto gc) {
+      constexpr int g = decltype(gc)::value;
+      const int G = G0 + g;
+      const int cbase = G * PW + L::col(lane);
+      double qn[NB][4];
+      T rnx[NB][4];
+      if constexpr (PIPE) {
+        if constexpr (g + 1 < GW)
+          load_unit(t, G + 1, qn, rnx);
+        else
+          load_unit(t + ww.stride < ww.end ? t + ww.stride : t, G0, qn, rnx);
+      } else {
+#pragma unroll
+        for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW, NT>(qa[ab], Q, row0, n, G, ab, lane);
+      }
+      double rn[NB][4];
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb) {
+        d4 D = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ab = 0; ab < NB; ++ab)
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) D = mfma(qa[ab][kk], cf[g].b(0, ab, jb, kk, lane), D);
+        if constexpr (!PIPE) load_rows(t, G, jb, ra[jb]);
+        T dq[4], rv[4];
+        to_rows(D, dq, lane);
+#pragma unroll
+        for (int m = 0; m < L::NR; ++m) {
+          const int64_t row = row0 + L::row(m, lane);
+          const bool ok = row < n;
+          T* v = rv + m * L::NC;
+#pragma unroll
+          for (int e = 0; e < L::NC; ++e) v[e] = ok ? ra[jb][m * L::NC + e] - dq[m * L::NC + e] : T(0);  // R - Q lambda
+          if (ok) L::store(R + row * K + cbase + jb * 16, v);
+        }
+        from_rows(rv, rn[jb], lane);
+      }
+      gram_tiles<NB>(acc[g], rn, rn);
+      if constexpr (PIPE)
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            qa[jb][e] = qn[jb][e];
+            ra[jb][e] = rnx[jb][e];
+          }
+    });
   }
-  finish_mfma<K, PW, true, perm_of<T>()>(acc, G, smem, part + (int64_t)blockIdx.x * pl.W, pl);
+  }
+  finish_mfma<K, PW, true, perm_of<T>(), GW>(acc, G0, smem, part + (int64_t)blockIdx.x * pl.W, pl);
 }
 
 // ------------------------------------------------------- X and P update
 // X += P lambda (line 8); unless `last`: P = R + P beta (line 13) and the
-// partial rho = <<P_new, R>> of the next iteration's line 6. FP32 with
-// single-block groups: operands of the next tile are loaded before the
-// products of the current one.
-template <typename T, int K, int PW, bool NT>
+// partial rho = <<P_new, R>> of the next iteration's line 6. Groups per wave
+// and pipelining as in the R update.
+template <typename T, int K, int PW, bool NT, int GW>
 __global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restrict__ X, T* __restrict__ Pm,
                                                            const T* __restrict__ R, const T* __restrict__ lam,
                                                            const T* __restrict__ beta, double* __restrict__ part,
@@ -607,19 +785,22 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restric
   using Gm = MGeo<K, PW>;
   using L = Lay<T>;
   constexpr int NB = Gm::NB;
+  static_assert(Gm::NG % GW == 0 && (GW == 1 || Gm::BREG), "groups per wave");
   __shared__ double smem[smem_doubles<K, PW, 2>()];
   const int lane = threadIdx.x & 63;
   const int64_t n = pl.n;
-  const WaveWork ww = wave_work<Gm::NG>((n + 15) / 16);
-  const int G = ww.group;
-  const int cbase = G * PW + L::col(lane);
-  Coeff<T, K, PW, 2> cf;
-  cf.load({lam, beta}, {true, !last}, pl, G, smem);
-  MAcc<NB> acc;
-  acc.zero();
+  const WaveWork ww = wave_work<Gm::NG / GW>((n + 15) / 16);
+  const int G0 = ww.group * GW;
+  Coeff<T, K, PW, 2> cf[GW];
+#pragma unroll
+  for (int g = 0; g < GW; ++g) cf[g].load({lam, beta}, {true, !last}, pl, G0 + g, smem);
+  MAcc<NB> acc[GW];
+#pragma unroll
+  for (int g = 0; g < GW; ++g) acc[g].zero();
   double pa[NB][4];
   T xa[NB][4], ra[NB][4];
-  auto load_rows = [&](int64_t t, int jb, T (&x)[4], T (&r)[4]) {
+  auto load_rows = [&](int64_t t, int G, int jb, T (&x)[4], T (&r)[4]) {
+    const int cbase = G * PW + L::col(lane);
 #pragma unroll
     for (int m = 0; m < L::NR; ++m) {
       const int64_t off = min(t * 16 + L::row(m, lane), n - 1) * K + cbase + jb * 16;
@@ -627,77 +808,144 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restric
       if (!last) L::template load_p<NT>(R + off, r + m * L::NC);
     }
   };
-  auto load_tile = [&](int64_t t, double (&pq)[NB][4], T (&x)[NB][4], T (&r)[NB][4]) {
+  auto load_unit = [&](int64_t t, int G, double (&pq)[NB][4], T (&x)[NB][4], T (&r)[NB][4]) {
 #pragma unroll
     for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW, NT>(pq[ab], Pm, t * 16, n, G, ab, lane);
 #pragma unroll
-    for (int jb = 0; jb < NB; ++jb) load_rows(t, jb, x[jb], r[jb]);
+    for (int jb = 0; jb < NB; ++jb) load_rows(t, G, jb, x[jb], r[jb]);
   };
   constexpr bool PIPE = sizeof(T) == 4 && NB == 1;
-  if (PIPE && ww.first < ww.end) load_tile(ww.first, pa, xa, ra);
+  if constexpr (sizeof(T) == 4 && GW == 2 && NB == 1) {
+    // both groups of a tile at once, every access a whole line of each row
+    const int c0 = G0 * PW;
+    float p2[2][4], x2[2][4], r2[2][4];
+    auto load_pair = [&](int64_t t, float (&pq)[2][4], float (&x)[2][4], float (&r)[2][4]) {
+      const int lim = tile_lim(t * 16, n);
+      pair_load_a<NT>(pq[0], pq[1], Pm + t * 16 * K, lim, K, c0, lane);
+      pair_load<NT>(x[0], x[1], X + t * 16 * K, lim, K, c0, lane);
+      if (!last) pair_load<NT>(r[0], r[1], R + t * 16 * K, lim, K, c0, lane);
+    };
+    if (ww.first < ww.end) load_pair(ww.first, p2, x2, r2);
+    for (int64_t t = ww.first; t < ww.end; t += ww.stride) {
+      const int64_t row0 = t * 16;
+      float pnx[2][4], xnx[2][4], rnx[2][4];
+      load_pair(t + ww.stride < ww.end ? t + ww.stride : t, pnx, xnx, rnx);
+      const bool ok = row0 + L::row(0, lane) < n;
+      float xv[2][4], pv[2][4], rv[2][4];
+      double pn[2][1][4], rd[2][1][4];
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        d4 Dx = {0.0, 0.0, 0.0, 0.0}, Dp = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) Dx = mfma(static_cast<double>(p2[g][kk]), cf[g].b(0, 0, 0, kk, lane), Dx);
+        float dx[4], dp[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        to_rows(Dx, dx, lane);
+        if (!last) {
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) Dp = mfma(static_cast<double>(p2[g][kk]), cf[g].b(1, 0, 0, kk, lane), Dp);
+          to_rows(Dp, dp, lane);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          xv[g][e] = x2[g][e] + dx[e];  // X + P lambda
+          rv[g][e] = (ok && !last) ? r2[g][e] : 0.0f;
+          pv[g][e] = (ok && !last) ? rv[g][e] + dp[e] : 0.0f;  // R + P beta
+        }
+      }
+      const int lim = tile_lim(row0, n);
+      pair_store<NT>(X + row0 * K, xv[0], xv[1], lim, K, c0, lane);
+      if (!last) {
+        pair_store<false>(Pm + row0 * K, pv[0], pv[1], lim, K, c0, lane);
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+          from_rows(pv[g], pn[g][0], lane);
+          from_rows(rv[g], rd[g][0], lane);
+          gram_tiles<1>(acc[g], pn[g], rd[g]);  // rho = <<P_new, R>>
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          p2[g][e] = pnx[g][e];
+          x2[g][e] = xnx[g][e];
+          r2[g][e] = rnx[g][e];
+        }
+    }
+  } else {
+  if (PIPE && ww.first < ww.end) load_unit(ww.first, G0, pa, xa, ra);
   for (int64_t t = ww.first; t < ww.end; t += ww.stride) {
     const int64_t row0 = t * 16;
-    double pnx[NB][4];
-    T xnx[NB][4], rnx[NB][4];
-    if constexpr (PIPE) {
-      load_tile(t + ww.stride < ww.end ? t + ww.stride : t, pnx, xnx, rnx);
-    } else {
+    static_for<GW>([&](auto gc) {
+      constexpr int g = decltype(gc)::value;
+      const int G = G0 + g;
+      const int cbase = G * PW + L::col(lane);
+      double pnx[NB][4];
+      T xnx[NB][4], rnx[NB][4];
+      if constexpr (PIPE) {
+        if constexpr (g + 1 < GW)
+          load_unit(t, G + 1, pnx, xnx, rnx);
+        else
+          load_unit(t + ww.stride < ww.end ? t + ww.stride : t, G0, pnx, xnx, rnx);
+      } else {
 #pragma unroll
-      for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW, NT>(pa[ab], Pm, row0, n, G, ab, lane);
-    }
-    double pn[NB][4], rd[NB][4];
+        for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW, NT>(pa[ab], Pm, row0, n, G, ab, lane);
+      }
+      double pn[NB][4], rd[NB][4];
 #pragma unroll
-    for (int jb = 0; jb < NB; ++jb) {
-      d4 Dx = {0.0, 0.0, 0.0, 0.0}, Dp = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int ab = 0; ab < NB; ++ab)
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) Dx = mfma(pa[ab][kk], cf.b(0, ab, jb, kk, lane), Dx);
-      if constexpr (!PIPE) load_rows(t, jb, xa[jb], ra[jb]);
-      T dx[4], dp[4], pv[4], rv[4];
-      to_rows(Dx, dx, lane);
-      if (!last) {
+      for (int jb = 0; jb < NB; ++jb) {
+        d4 Dx = {0.0, 0.0, 0.0, 0.0}, Dp = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int ab = 0; ab < NB; ++ab)
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) Dp = mfma(pa[ab][kk], cf.b(1, ab, jb, kk, lane), Dp);
-        to_rows(Dp, dp, lane);
-      }
+          for (int kk = 0; kk < 4; ++kk) Dx = mfma(pa[ab][kk], cf[g].b(0, ab, jb, kk, lane), Dx);
+        if constexpr (!PIPE) load_rows(t, G, jb, xa[jb], ra[jb]);
+        T dx[4], dp[4], pv[4], rv[4];
+        to_rows(Dx, dx, lane);
+        if (!last) {
 #pragma unroll
-      for (int m = 0; m < L::NR; ++m) {
-        const int64_t row = row0 + L::row(m, lane);
-        const bool ok = row < n;
-        const int64_t off = row * K + cbase + jb * 16;
-        T x[L::NC];
+          for (int ab = 0; ab < NB; ++ab)
 #pragma unroll
-        for (int e = 0; e < L::NC; ++e) x[e] = xa[jb][m * L::NC + e] + dx[m * L::NC + e];  // X + P lambda
-        if (ok) L::template store_p<NT>(X + off, x);
-        T* pvm = pv + m * L::NC;
-        T* rvm = rv + m * L::NC;
-#pragma unroll
-        for (int e = 0; e < L::NC; ++e) {
-          rvm[e] = (ok && !last) ? ra[jb][m * L::NC + e] : T(0);
-          pvm[e] = (ok && !last) ? rvm[e] + dp[m * L::NC + e] : T(0);  // R + P beta
+            for (int kk = 0; kk < 4; ++kk) Dp = mfma(pa[ab][kk], cf[g].b(1, ab, jb, kk, lane), Dp);
+          to_rows(Dp, dp, lane);
         }
-        if (ok && !last) L::store(Pm + off, pvm);
-      }
-      if (!last) {
-        from_rows(pv, pn[jb], lane);
-        from_rows(rv, rd[jb], lane);
-      }
-    }
-    if (!last) gram_tiles<NB>(acc, pn, rd);  // rho = <<P_new, R>>
-    if constexpr (PIPE)
 #pragma unroll
-      for (int jb = 0; jb < NB; ++jb)
+        for (int m = 0; m < L::NR; ++m) {
+          const int64_t row = row0 + L::row(m, lane);
+          const bool ok = row < n;
+          const int64_t off = row * K + cbase + jb * 16;
+          T x[L::NC];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          pa[jb][e] = pnx[jb][e];
-          xa[jb][e] = xnx[jb][e];
-          ra[jb][e] = rnx[jb][e];
+          for (int e = 0; e < L::NC; ++e) x[e] = xa[jb][m * L::NC + e] + dx[m * L::NC + e];  // X + P lambda
+          if (ok) L::template store_p<NT>(X + off, x);
+          T* pvm = pv + m * L::NC;
+          T* rvm = rv + m * L::NC;
+#pragma unroll
+          for (int e = 0; e < L::NC; ++e) {
+            rvm[e] = (ok && !last) ? ra[jb][m * L::NC + e] : T(0);
+            pvm[e] = (ok && !last) ? rvm[e] + dp[m * L::NC + e] : T(0);  // R + P beta
+          }
+          if (ok && !last) L::store(Pm + off, pvm);
         }
+        if (!last) {
+          from_rows(pv, pn[jb], lane);
+          from_rows(rv, rd[jb], lane);
+        }
+      }
+      if (!last) gram_tiles<NB>(acc[g], pn, rd);  // rho = <<P_new, R>>
+      if constexpr (PIPE)
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            pa[jb][e] = pnx[jb][e];
+            xa[jb][e] = xnx[jb][e];
+            ra[jb][e] = rnx[jb][e];
+          }
+    });
   }
-  finish_mfma<K, PW, false, perm_of<T>()>(acc, G, smem, part + (int64_t)blockIdx.x * pl.W, pl);
+  }
+  finish_mfma<K, PW, false, perm_of<T>(), GW>(acc, G0, smem, part + (int64_t)blockIdx.x * pl.W, pl);
 }
 
 // ---------------------------------------------------------------- SpMM
@@ -1252,6 +1500,17 @@ void mfma_sp_grid(Plan& pl) {
     // together exceed the 256 MiB memory-side cache
     const int64_t working = 4 * pl.n * pl.k * elem + pl.nnz * (elem + 4) + 4 * (pl.n + 1);
     pl.nt[prec] = working > (int64_t(256) << 20);
+    // column groups per wave of the update passes: a whole 128-byte line of
+    // every row where one 16-column FP32 group covers only half of one (both
+    // groups then move in whole-line instructions; BCG_UPDATE_GW = 1 or 2
+    // overrides for 16-column groups)
+    const int ng = pl.mfma > 0 ? pl.k / pl.mfma : 1;
+    int gw = (prec == 1 && pl.mfma == 16 && ng % 2 == 0) ? 2 : 1;
+    if (const char* e = std::getenv("BCG_UPDATE_GW")) {
+      const int v = std::atoi(e);
+      if ((v == 1 || v == 2) && ng % v == 0 && (v == 1 || pl.mfma == 16)) gw = v;
+    }
+    pl.ugw[prec] = gw;
   }
 }
 
@@ -1297,6 +1556,14 @@ void launch_spmm_mfma(const Plan& pl, const int32_t* rowptr, const int32_t* coli
   });
 }
 
+template <typename F>
+void with_gw(int gw, F&& f) {
+  if (gw == 2)
+    f(std::integral_constant<int, 2>());
+  else
+    f(std::integral_constant<int, 1>());
+}
+
 template <typename T>
 void launch_update_r_mfma(const Plan& pl, T* R, const T* Q, const T* lam, double* part, const DevState* st,
                           hipStream_t s) {
@@ -1304,11 +1571,17 @@ void launch_update_r_mfma(const Plan& pl, T* R, const T* Q, const T* lam, double
   const bool nt = pl.nt[std::is_same<T, float>::value ? 1 : 0] != 0;
   dispatch_mfma(pl, [&](auto Kc, auto Wc) {
     constexpr int K = decltype(Kc)::value, W = decltype(Wc)::value;
-    if (stream_nt<T, K, W>() && nt)
-      hipLaunchKernelGGL((k_update_r_mfma<T, K, W, stream_nt<T, K, W>()>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, R,
-                         Q, lam, part, st);
-    else
-      hipLaunchKernelGGL((k_update_r_mfma<T, K, W, false>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, R, Q, lam, part, st);
+    with_gw(pl.ugw[std::is_same<T, float>::value ? 1 : 0], [&](auto Gc) {
+      constexpr int GW = (MGeo<K, W>::NG % decltype(Gc)::value == 0 && (decltype(Gc)::value == 1 || W == 16))
+                             ? decltype(Gc)::value
+                             : 1;
+      if (stream_nt<T, K, W, GW>() && nt)
+        hipLaunchKernelGGL((k_update_r_mfma<T, K, W, stream_nt<T, K, W, GW>(), GW>), dim3(pl.nwg), dim3(kBlock), 0, s,
+                           pl, R, Q, lam, part, st);
+      else
+        hipLaunchKernelGGL((k_update_r_mfma<T, K, W, false, GW>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, R, Q, lam,
+                           part, st);
+    });
   });
 }
 
@@ -1319,12 +1592,17 @@ void launch_update_xp_mfma(const Plan& pl, T* X, T* P, const T* R, const T* lam,
   const bool nt = pl.nt[std::is_same<T, float>::value ? 1 : 0] != 0;
   dispatch_mfma(pl, [&](auto Kc, auto Wc) {
     constexpr int K = decltype(Kc)::value, W = decltype(Wc)::value;
-    if (stream_nt<T, K, W>() && nt)
-      hipLaunchKernelGGL((k_update_xp_mfma<T, K, W, stream_nt<T, K, W>()>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, X,
-                         P, R, lam, beta, part, st);
-    else
-      hipLaunchKernelGGL((k_update_xp_mfma<T, K, W, false>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, X, P, R, lam, beta,
-                         part, st);
+    with_gw(pl.ugw[std::is_same<T, float>::value ? 1 : 0], [&](auto Gc) {
+      constexpr int GW = (MGeo<K, W>::NG % decltype(Gc)::value == 0 && (decltype(Gc)::value == 1 || W == 16))
+                             ? decltype(Gc)::value
+                             : 1;
+      if (stream_nt<T, K, W, GW>() && nt)
+        hipLaunchKernelGGL((k_update_xp_mfma<T, K, W, stream_nt<T, K, W, GW>(), GW>), dim3(pl.nwg), dim3(kBlock), 0,
+                           s, pl, X, P, R, lam, beta, part, st);
+      else
+        hipLaunchKernelGGL((k_update_xp_mfma<T, K, W, false, GW>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, X, P, R, lam,
+                           beta, part, st);
+    });
   });
 }
 

@@ -750,6 +750,24 @@ int bcg_create(const bcg_csr* A, int k, int subalgebra, int p, bcg_handle** out)
     delete h;
     return fail(BCG_EHIP, "copying the CSR matrix failed: %s", hipGetErrorString(e));
   }
+  // the CSR contents, before any kernel follows a row range or gathers a column
+  DevState z{};
+  e = hipMemcpy(h->st, &z, sizeof z, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    launch_check_csr(h->rowptr, h->colind, h->n, h->nnz, &h->st->status, nullptr);
+    e = hipMemcpy(&z, h->st, sizeof z, hipMemcpyDeviceToHost);
+  }
+  if (e != hipSuccess) {
+    free_all(h);
+    delete h;
+    return fail(BCG_EHIP, "checking the CSR matrix failed: %s", hipGetErrorString(e));
+  }
+  if (z.status != 0) {
+    free_all(h);
+    delete h;
+    return fail(BCG_EINVAL, "malformed CSR: needs rowptr[0] = 0, rowptr non-decreasing, rowptr[n] = nnz "
+                            "and every column index in [0, n)");
+  }
   *out = h;
   return BCG_OK;
 }
@@ -909,17 +927,21 @@ int bcg_set_row_schedule(bcg_handle* h, const int32_t* order) {
   int rc;
   if (!h->sched && (rc = dalloc(&h->sched, h->n))) return rc;
   HIP_TRY(hipMemcpyAsync(h->sched, order, sizeof(int32_t) * h->n, hipMemcpyDeviceToDevice, h->stream));
-  // range check (memory safety of the product); the flag lives in the state
+  // permutation check (memory safety of the product, and every row of Q
+  // written once); the row counters borrow the workspace of Q, the flag lives
+  // in the state
   DevState z{};
   HIP_TRY(hipMemcpyAsync(h->st, &z, sizeof z, hipMemcpyHostToDevice, h->stream));
-  launch_check_range(h->sched, h->n, &h->st->status, h->stream);
+  int* seen = reinterpret_cast<int*>(h->Q);
+  HIP_TRY(hipMemsetAsync(seen, 0, sizeof(int) * h->n, h->stream));
+  launch_check_perm(h->sched, h->n, seen, &h->st->status, h->stream);
   HIP_TRY(hipGetLastError());
   DevState out{};
   if ((rc = read_state(h, &out))) return rc;
   if (out.status != 0) {
     h->pl.sched = nullptr;
     (void)rebuild_sell(h);  // the SELL copy follows the natural order too
-    return fail(BCG_EINVAL, "row schedule has entries outside [0, n)");
+    return fail(BCG_EINVAL, "row schedule is not a permutation of 0..n-1");
   }
   h->pl.sched = h->sched;
   return rebuild_sell(h);

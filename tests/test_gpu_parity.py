@@ -95,6 +95,25 @@ def test_fixed_iterations_k_p_grid(k, variant, p):
     assert rel(host(Xg), Xo) <= FIXED_TOL
 
 
+@pytest.mark.parametrize("gw", ["1", "2"])
+@pytest.mark.parametrize("k,variant,p", [(32, "hybrid", 16), (64, "hybrid", 4), (128, "hybrid", 16),
+                                         (128, "global", 1), (32, "parallel", 1)])
+def test_update_groups_per_wave(monkeypatch, k, variant, p, gw):
+    # the matrix-core update passes with one or two column groups per wave
+    # (two: both groups' rows move as whole lines); FP64 iterates against the
+    # oracle, ragged row count
+    monkeypatch.setenv("BCG_UPDATE_GW", gw)
+    log(f"groups per wave {gw}: k={k} {variant} p={p}")
+    N = 29
+    A = stencil_csr(2, N, cell_coefficients(2, N, 0.7))
+    B = rhs(A.shape[0], k, "normal", seed=70 + k)
+    Xo, io = oracle_solve(A, B, variant, p, tol=0.0, maxit=5)
+    s = _solver(A, k, variant, p)
+    Xg, ig = s.solve(dev(B), tol=0.0, maxit=5)
+    assert ig["iterations"] == io["iterations"] == 5
+    assert rel(host(Xg), Xo) <= FIXED_TOL
+
+
 # ---------------------------------------------------- converged solutions
 def _converged_case(A, B, variant, p, tol=1e-8, maxit=5000):
     Xo, io = oracle_solve(A, B, variant, p, tol=tol, maxit=maxit)
@@ -372,18 +391,52 @@ def test_row_schedule_random_and_tiled(k, variant, p):
         assert rel(host(Xn), Xo) <= FIXED_TOL
 
 
-def test_row_schedule_rejects_out_of_range():
+@pytest.mark.parametrize("fault", ["out_of_range", "negative", "duplicate"])
+def test_row_schedule_rejects_non_permutation(fault):
     P = _lib()
     A = stencil_csr(2, 9)
     s = _solver(A, 8, "block", 0)
-    bad = np.arange(A.shape[0], dtype=np.int32)
-    bad[3] = A.shape[0]
+    bad = np.arange(A.shape[0], dtype=np.int32)[::-1].copy()
+    if fault == "out_of_range":
+        bad[3] = A.shape[0]
+    elif fault == "negative":
+        bad[3] = -1
+    else:
+        bad[7] = bad[40]      # row bad[7] is never computed, bad[40] twice
     with pytest.raises(P.BCGError) as e:
         s.set_row_schedule(dev(bad))
     assert e.value.status == oracle.EINVAL
     B = rhs(A.shape[0], 8, "uniform")
     Xo, _ = oracle_solve(A, B, "block", 0, tol=0.0, maxit=5)
     Xg, _ = s.solve(dev(B), tol=0.0, maxit=5)      # still the natural order
+    assert rel(host(Xg), Xo) <= FIXED_TOL
+
+
+@pytest.mark.parametrize("fault", ["rowptr0", "decreasing", "rowptr_n", "col_high", "col_negative"])
+def test_create_rejects_malformed_csr(fault):
+    # the device check at create returns EINVAL before any kernel follows a
+    # row range; the arrays stay within their allocations in every case
+    P = _lib()
+    A = stencil_csr(2, 9)
+    rp, ci, va = A.indptr.astype(np.int32).copy(), A.indices.astype(np.int32).copy(), A.data.copy()
+    if fault == "rowptr0":
+        rp[0] = 1
+    elif fault == "decreasing":
+        rp[10] = rp[9] - 1
+    elif fault == "rowptr_n":
+        rp[-1] = rp[-1] - 1
+    elif fault == "col_high":
+        ci[17] = A.shape[0]
+    else:
+        ci[17] = -3
+    with pytest.raises(P.BCGError) as e:
+        P.BCG(dev(rp), dev(ci), dev(va), k=8, subalgebra="block")
+    assert e.value.status == oracle.EINVAL
+    # the well-formed matrix still builds and solves
+    s = _solver(A, 8, "block", 0)
+    B = rhs(A.shape[0], 8, "uniform")
+    Xg, _ = s.solve(dev(B), tol=0.0, maxit=3)
+    Xo, _ = oracle_solve(A, B, "block", 0, tol=0.0, maxit=3)
     assert rel(host(Xg), Xo) <= FIXED_TOL
 
 

@@ -55,10 +55,11 @@ def test_refine_reaches_fp64_accuracy(variant, p):
 
 
 FP32_CASES = [(16, "block", 0), (16, "hybrid", 4), (16, "parallel", 1), (32, "block", 0), (64, "hybrid", 32),
-              (48, "hybrid", 16), (8, "hybrid", 4), (12, "hybrid", 3)]
+              (48, "hybrid", 16), (8, "hybrid", 4), (12, "hybrid", 3), (32, "hybrid", 16), (64, "hybrid", 8),
+              (128, "hybrid", 16), (128, "global", 1)]
 
 
-@pytest.mark.parametrize("path", ["default", "no_mfma", "wide_offsets"])
+@pytest.mark.parametrize("path", ["default", "no_mfma", "wide_offsets", "one_group_per_wave"])
 @pytest.mark.parametrize("k,variant,p", FP32_CASES)
 def test_fp32_inner_iterations_match_oracle(monkeypatch, k, variant, p, path):
     """One refinement step with 6 FP32 inner iterations against the oracle's.
@@ -71,6 +72,8 @@ def test_fp32_inner_iterations_match_oracle(monkeypatch, k, variant, p, path):
         monkeypatch.setenv("BCG_NO_MFMA", "1")
     if path == "wide_offsets":  # 64-bit offsets in the sparse products
         monkeypatch.setenv("BCG_WIDE_OFFSETS", "1")
+    if path == "one_group_per_wave":  # update passes without paired 16-column groups
+        monkeypatch.setenv("BCG_UPDATE_GW", "1")
     from oracle import refine
     log(f"fp32 inner k={k} {variant} p={p} {path}")
     P = _P()
@@ -83,7 +86,9 @@ def test_fp32_inner_iterations_match_oracle(monkeypatch, k, variant, p, path):
     assert io["status"] == info["status"] == oracle.NOT_CONVERGED
     assert not io["fp64_fallback"] and info["fp64_fallback"] == 0
     assert io["iterations"] == info["iterations"] == 6
-    assert rel(host(X), Xo) <= 1e-4
+    err = rel(host(X), Xo)
+    log(f"fp32 inner k={k} {variant} p={p} {path}: rel {err:.3e}")
+    assert err <= 1e-4
 
 
 def test_refine_stagnation_falls_back_to_fp64():
