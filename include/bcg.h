@@ -66,9 +66,13 @@ typedef enum {
 } bcg_subalgebra;
 
 typedef enum {
-  BCG_FP64 = 0,       /* everything in FP64 */
-  BCG_FP32_REFINE = 1 /* FP32 inner block CG (FP64 block products and small
-                         solves), FP64 outer iterative refinement */
+  BCG_FP64 = 0,         /* everything in FP64 */
+  BCG_FP32_REFINE = 1,  /* FP32 inner block CG (FP64 block products and small
+                           solves), FP64 outer iterative refinement; each
+                           outer step restarts the inner iteration */
+  BCG_FP32_RELIABLE = 2 /* the same FP32 iteration kept running across the
+                           FP64 corrections: residual replacement (reliable
+                           updates) instead of restarts */
 } bcg_precision;
 
 typedef struct bcg_handle bcg_handle;
@@ -127,6 +131,7 @@ int bcg_set_stream(bcg_handle *h, void *hip_stream);
 
 /*
  * bcg_set_precision -- choose FP64 or FP32 inner solves with FP64 refinement.
+ * BCG_FP32_REFINE (restarted inner solves):
  *   inner_tol    depth of the inner FP32 solves: each asks for the remaining
  *                reduction 0.5 tol / ratio, but no deeper than inner_tol / 4
  *                (0 <= inner_tol < 1; 0 selects 4e-6 for groups of p <= 16
@@ -134,8 +139,24 @@ int bcg_set_stream(bcg_handle *h, void *hip_stream);
  *                accuracy sooner).
  *   inner_maxit  iteration cap of each inner solve (>= 1; default 1000).
  *   max_outer    cap on refinement steps (>= 1; default 50).
- * Not in the paper: the mixed-precision form keeps the block products, the
- * Cholesky and LU solves and the true residual in FP64.
+ * BCG_FP32_RELIABLE (residual replacement):
+ *   inner_tol    replacement threshold delta: the FP64 correction and
+ *                residual replacement happen whenever the FP32 recursive
+ *                residual has fallen to delta times its value at the last
+ *                correction, or to tol (0 < delta < 1; 0 selects 1e-2).
+ *   inner_maxit  cap on FP32 iterations between two corrections.
+ *   max_outer    cap on corrections.
+ *   After a correction X += s D, R = B - A X (FP64), s' = max_j ||R_j||,
+ *   the iteration continues on the scaled system with R32 = R / s', its
+ *   search direction P32 *= s / s' and the last line-6 product rho *=
+ *   (s / s')^2, from line 10 (residual replacement: van der Vorst and Ye,
+ *   SIAM J. Sci. Comput. 22 (2000); reliable updates: Sleijpen and van der
+ *   Vorst, Computing 56 (1996)).
+ * Both forms stop on the FP64 true residual, and finish with the FP64
+ * iteration from the current X if a correction fails to halve the largest
+ * relative residual (bcg_info.fp64_fallback). Not in the paper: the
+ * mixed-precision forms keep the block products, the Cholesky and LU
+ * solves and the true residual in FP64.
  */
 int bcg_set_precision(bcg_handle *h, int mode, double inner_tol, int inner_maxit, int max_outer);
 

@@ -19,7 +19,7 @@ BCG_ENOMEM = -3
 BCG_EHIP = -4
 
 SUBALGEBRA = {"block": 0, "global": 1, "parallel": 2, "hybrid": 3}
-PRECISION = {"fp64": 0, "fp32_refine": 1}
+PRECISION = {"fp64": 0, "fp32_refine": 1, "fp32_reliable": 2}
 PRECOND = {"none": 0, "jacobi": 1}
 STATUS_NAME = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EBREAKDOWN", -3: "ENOMEM", -4: "EHIP"}
 

@@ -92,7 +92,7 @@ void launch_residual(const Plan& pl, const int32_t* rowptr, const int32_t* colin
 // FP32 inner start: s = max_j sqrt(norms_j); R32 = R64/s; P32 = R32; D32 = 0;
 // <<R32,R32>> partial (FP64 accumulation) and norms partial.
 void launch_cast_init(const Plan& pl, const double* R64, const double* norms, float* R32, float* P32,
-                      float* D32, double* scale, double* part, hipStream_t s);
+                      float* D32, double* scale, double* part, hipStream_t s, double pfac = 0.0);
 template <typename T>
 void launch_spmm_product(const Plan& pl, const int32_t* rowptr, const int32_t* colind, const T* vals,
                          const T* P, T* Q, double* part, const DevState* st, hipStream_t s);
@@ -134,6 +134,8 @@ void launch_conv_beta(const Plan& pl, const double* red_new, const double* r0, c
                       double* beta, float* beta32, double* ws, double* ratios, DevState* st, double tol,
                       int it, int maxit, hipStream_t s);
 void launch_axpy_scaled(int64_t count, double* X, const float* D, const double* scale, hipStream_t s);
+// x *= c (count entries)
+void launch_scale_vec(double* x, int64_t count, double c, hipStream_t s);
 void launch_sampled_outer(int64_t n, int k, const int32_t* rowptr, const int32_t* colind, const double* Y,
                           const double* X, double alpha, double* out, hipStream_t s);
 void launch_cast_values(int64_t nnz, const double* v, float* v32, hipStream_t s);

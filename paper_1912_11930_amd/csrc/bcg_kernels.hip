@@ -261,10 +261,15 @@ __global__ __launch_bounds__(kBlock) void k_residual(Plan pl, const int32_t* __r
 
 // FP32 inner start of a refinement step.
 template <int RB, int NAB>
+// R32 = R64 / s with s = max_j sqrt(norms[j]) (stored to *scale), D32 = 0,
+// and P32 = R32 (pfac = 0: a fresh start) or P32 *= pfac rounded to FP32
+// (pfac != 0: the search direction in the units of the new scale, residual
+// replacement); the partial <<R32, R32>> with the column norms.
 __global__ __launch_bounds__(kBlock) void k_cast_init(Plan pl, const double* __restrict__ R64,
                                                       const double* __restrict__ norms, float* __restrict__ R32,
                                                       float* __restrict__ P32, float* __restrict__ D32,
-                                                      double* __restrict__ scale, double* __restrict__ part) {
+                                                      double* __restrict__ scale, double* __restrict__ part,
+                                                      double pfac) {
   __shared__ float Rs[kTileElems];
   __shared__ double scratch[kBlock * RB * RB];
   __shared__ double s_sh;
@@ -285,7 +290,7 @@ __global__ __launch_bounds__(kBlock) void k_cast_init(Plan pl, const double* __r
     for (int e = tid; e < tr.ne; e += kBlock) {
       const float v = static_cast<float>(R64[tr.base + e] / s);
       R32[tr.base + e] = v;
-      P32[tr.base + e] = v;
+      P32[tr.base + e] = pfac == 0.0 ? v : P32[tr.base + e] * static_cast<float>(pfac);
       D32[tr.base + e] = 0.0f;
       Rs[e] = v;
     }
@@ -1593,11 +1598,21 @@ void launch_residual(const Plan& pl, const int32_t* rowptr, const int32_t* colin
 }
 
 void launch_cast_init(const Plan& pl, const double* R64, const double* norms, float* R32, float* P32, float* D32,
-                      double* scale, double* part, hipStream_t s) {
+                      double* scale, double* part, hipStream_t s, double pfac) {
   dispatch_shape(pl, [&](auto RB, auto NAB) {
     hipLaunchKernelGGL((k_cast_init<decltype(RB)::value, decltype(NAB)::value>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, R64, norms, R32, P32, D32,
-                       scale, part);
+                       scale, part, pfac);
   });
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale_vec(double* __restrict__ x, int64_t count, double c) {
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < count; e += (int64_t)gridDim.x * kBlock) x[e] *= c;
+}
+
+void launch_scale_vec(double* x, int64_t count, double c, hipStream_t s) {
+  const int64_t blocks = (count + kBlock - 1) / kBlock;
+  const int grid = static_cast<int>(blocks < 1024 ? (blocks > 0 ? blocks : 1) : 1024);
+  hipLaunchKernelGGL(k_scale_vec, dim3(grid), dim3(kBlock), 0, s, x, count, c);
 }
 
 template <typename T>

@@ -241,6 +241,25 @@ int fetch_norms(bcg_handle* h, const double* red, std::vector<double>& out) {
 
 bool decoupled(const bcg_handle* h) { return h->p == 1 && (h->variant == BCG_PARALLEL || h->variant == BCG_HYBRID); }
 
+// X += P lambda; unless `last`: P = R + P beta and the partial <<P, R>>
+// (line 6 of the next iteration) in partR.
+template <typename T>
+void enqueue_update_xp(bcg_handle* h, const IterBuffers<T>& b, int it) {
+  const Plan& pl = h->pl;
+  hipStream_t s = h->stream;
+  const bool mfma = h->path == RowPath::mfma, fast = mfma || h->path == RowPath::fast;
+  timed(h, BCG_K_UPDATE_XP, it, [&] {
+    if (mfma)
+      launch_update_xp_mfma<T>(pl, b.X, b.P, b.R, b.lam, b.beta, h->partR, h->st, s);
+    else if (fast)
+      launch_update_xp_fast<T>(pl, b.X, b.P, b.R, b.lam, b.beta, h->partR, h->st, s);
+    else
+      launch_update_xp<T>(pl, b.X, b.P, b.R, b.lam, b.beta, h->partR, h->st, s);
+  });
+  if (!fast && !pl.fused)
+    timed(h, BCG_K_PRODUCT, it + 1, [&] { launch_product<T>(pl, b.P, b.R, h->partR, h->st, s); });
+}
+
 // Enqueues one iteration (number `it`) of Algorithm 1 in precision T.
 template <typename T>
 void enqueue_iteration(bcg_handle* h, const IterBuffers<T>& b, double tol, int it, int maxit) {
@@ -285,16 +304,7 @@ void enqueue_iteration(bcg_handle* h, const IterBuffers<T>& b, double tol, int i
   });
   // line 8 and line 13 with the partial products of line 6 for the next
   // iteration (on the last iteration only line 8)
-  timed(h, BCG_K_UPDATE_XP, it, [&] {
-    if (mfma)
-      launch_update_xp_mfma<T>(pl, b.X, b.P, b.R, b.lam, b.beta, h->partR, h->st, s);
-    else if (fast)
-      launch_update_xp_fast<T>(pl, b.X, b.P, b.R, b.lam, b.beta, h->partR, h->st, s);
-    else
-      launch_update_xp<T>(pl, b.X, b.P, b.R, b.lam, b.beta, h->partR, h->st, s);
-  });
-  if (!fast && !pl.fused)
-    timed(h, BCG_K_PRODUCT, it + 1, [&] { launch_product<T>(pl, b.P, b.R, h->partR, h->st, s); });
+  enqueue_update_xp<T>(h, b, it);
 }
 
 // Iterations to enqueue next: half the predicted remaining count (from the
@@ -520,6 +530,131 @@ int solve_refine(bcg_handle* h, const double* B, double* X, double tol, int maxi
     info.iterations += its;
     return rc;
   }
+}
+
+// Default replacement threshold of the residual-replacement form.
+double effective_delta(double inner_tol) { return inner_tol > 0.0 ? inner_tol : 1e-2; }
+
+// Mixed precision with residual replacement: one FP32 iteration of
+// Algorithm 1 on the scaled system A D = R / s whose search direction is kept
+// across the FP64 corrections. It runs until its recursive residual (in units
+// of the true relative residual) reaches max(tol, delta * last), where last is
+// the true relative residual at the previous correction; then X += s D, the
+// FP64 residual R = B - A X replaces the FP32 one in a new scale s', P32 and
+// the last line-6 product rho are rescaled by s / s' and (s / s')^2, and the
+// iteration resumes at line 10 (rho_new, beta, P = R + P beta; the X/P pass
+// runs with lambda = 0, so D stays 0).
+int solve_reliable(bcg_handle* h, const double* B, double* X, double tol, int maxit) {
+  const Plan& pl = h->pl;
+  int rc;
+  if ((rc = alloc_fp32(h))) return rc;
+  bcg_info& info = h->info;
+  const double delta = effective_delta(h->inner_tol);
+  timed(h, BCG_K_RESIDUAL, 0, [&] {
+    launch_residual(pl, h->rowptr, h->colind, h->vals, B, X, h->R, nullptr, h->partN, 0, h->stream);
+  });
+  timed(h, BCG_K_REDUCE, 0, [&] { launch_reduce(pl, h->partN, h->rnew, pl.W, nullptr, h->stream); });
+  HIP_TRY(hipGetLastError());
+  std::vector<double> norms2, r0;
+  if ((rc = fetch_norms(h, h->rnew, norms2))) return rc;
+  bool all_zero = false;
+  if ((rc = set_reference(h, norms2, r0, &all_zero, decoupled(h)))) return rc;
+  h->ref_r0 = r0;
+  if (all_zero) return BCG_OK;
+  auto scale_of = [&](const std::vector<double>& n2) {
+    double m = 0.0;
+    for (double v : n2) m = std::max(m, std::sqrt(v));
+    return m;
+  };
+  IterBuffers<float> b{h->vals32, h->D32, h->R32, h->P32, h->Q32, h->lam32, h->beta32};
+  h->path = row_path(h->pl, true);
+  // fresh start: R32 = R / s, P32 = R32, D32 = 0, rho = <<R32, R32>>
+  double s = scale_of(norms2);
+  if ((rc = reset_state(h))) return rc;
+  timed(h, BCG_K_RESIDUAL, 0, [&] {
+    launch_cast_init(pl, h->R, h->rnew + pl.E, h->R32, h->P32, h->D32, h->scale, h->partR, h->stream);
+  });
+  if (!pl.fused)
+    timed(h, BCG_K_PRODUCT, 0, [&] { launch_product<float>(pl, h->R32, h->R32, h->partR, nullptr, h->stream); });
+  timed(h, BCG_K_REDUCE, 0, [&] { launch_reduce(pl, h->partR, h->rho, pl.W, nullptr, h->stream); });
+  // stop rule of the FP32 iteration in units of the true relative residual
+  std::vector<double> ref(h->k);
+  auto set_ref = [&](double sc) -> int {
+    for (int j = 0; j < h->k; ++j) ref[j] = r0[j] / sc;
+    HIP_TRY(hipMemcpyAsync(h->r0, ref.data(), sizeof(double) * h->k, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));  // ref is reused
+    return BCG_OK;
+  };
+  if ((rc = set_ref(s))) return rc;
+  double last = max_ratio(norms2, r0);
+  bool fallback = false;
+  int corrections = 0;
+  for (;;) {
+    const double itol = std::max(tol, delta * last);
+    DevState fin{};
+    if ((rc = run_iterations<float>(h, b, itol, h->inner_maxit, &fin))) return rc;
+    info.iterations += fin.iter;
+    if (fin.status < 0) {
+      fallback = true;  // FP32 breakdown: the FP64 iteration from the last correction's X
+      break;
+    }
+    // correction and true residual
+    timed(h, BCG_K_RESIDUAL, 0, [&] { launch_axpy_scaled(h->n * h->k, X, h->D32, h->scale, h->stream); });
+    timed(h, BCG_K_RESIDUAL, 0, [&] {
+      launch_residual(pl, h->rowptr, h->colind, h->vals, B, X, h->R, nullptr, h->partN, 0, h->stream);
+    });
+    timed(h, BCG_K_REDUCE, 0, [&] { launch_reduce(pl, h->partN, h->rnew, pl.W, nullptr, h->stream); });
+    HIP_TRY(hipGetLastError());
+    if ((rc = fetch_norms(h, h->rnew, norms2))) return rc;
+    ++corrections;
+    info.outer_iterations = corrections;
+    const double ratio = max_ratio(norms2, r0);
+    for (int j = 0; j < h->k; ++j) h->host_ratios[j] = r0[j] == 0.0 ? 0.0 : std::sqrt(norms2[j]) / r0[j];
+    if (!(ratio == ratio)) return fail(BCG_EBREAKDOWN, "non-finite residual during refinement");
+    if (ratio <= tol) return BCG_OK;
+    if (!(ratio <= 0.5 * last)) {
+      fallback = true;  // no progress since the last correction
+      break;
+    }
+    if (corrections >= h->max_outer) return BCG_NOT_CONVERGED;
+    last = ratio;
+    // residual replacement in the new scale s'
+    const double s_new = scale_of(norms2), f = s / s_new;
+    s = s_new;
+    if ((rc = set_ref(s))) return rc;
+    if ((rc = reset_state(h))) return rc;
+    timed(h, BCG_K_SMALL, 0, [&] { launch_scale_vec(h->rho, pl.E, f * f, h->stream); });
+    timed(h, BCG_K_RESIDUAL, 0, [&] {
+      launch_cast_init(pl, h->R, h->rnew + pl.E, h->R32, h->P32, h->D32, h->scale, h->partN, h->stream, f);
+    });
+    if (!pl.fused)
+      timed(h, BCG_K_PRODUCT, 0, [&] { launch_product<float>(pl, h->R32, h->R32, h->partN, nullptr, h->stream); });
+    // line 10-12 with the replaced residual (no stop: its ratio is above itol)
+    timed(h, BCG_K_SMALL, 0, [&] {
+      launch_reduce_beta(pl, h->partN, pl.nwg, h->rnew, h->r0, h->rho, h->beta, h->beta32, h->ws, h->ratios, h->st,
+                         std::max(tol, delta * last), 0, INT32_MAX, h->stream);
+    });
+    // line 13 (lambda = 0 leaves D = 0) and the next iteration's line 6
+    HIP_TRY(hipMemsetAsync(h->lam32, 0, sizeof(float) * pl.E, h->stream));
+    enqueue_update_xp<float>(h, b, 0);
+    timed(h, BCG_K_REDUCE, 0, [&] { launch_reduce(pl, h->partR, h->rho, pl.W, nullptr, h->stream); });
+    HIP_TRY(hipGetLastError());
+    DevState chk{};
+    if ((rc = read_state(h, &chk))) return rc;
+    if (chk.done || chk.last) {
+      if (chk.status < 0) {
+        fallback = true;  // beta breakdown after the replacement
+        break;
+      }
+      return fail(BCG_EHIP, "residual replacement: the stop rule fired on the replaced residual");
+    }
+  }
+  (void)fallback;
+  info.fp64_fallback = 1;
+  int its = 0;
+  rc = solve_fp64(h, B, X, tol, maxit, &r0, &its);
+  info.iterations += its;
+  return rc;
 }
 
 void free_sell(bcg_handle* h) {
@@ -788,7 +923,8 @@ int bcg_set_stream(bcg_handle* h, void* hip_stream) {
 
 int bcg_set_precision(bcg_handle* h, int mode, double inner_tol, int inner_maxit, int max_outer) {
   if (!h) return fail(BCG_EINVAL, "handle is NULL");
-  if (mode != BCG_FP64 && mode != BCG_FP32_REFINE) return fail(BCG_EINVAL, "unknown precision mode %d", mode);
+  if (mode != BCG_FP64 && mode != BCG_FP32_REFINE && mode != BCG_FP32_RELIABLE)
+    return fail(BCG_EINVAL, "unknown precision mode %d", mode);
   if (!(inner_tol >= 0.0 && inner_tol < 1.0)) return fail(BCG_EINVAL, "inner_tol must be in [0, 1)");
   if (inner_maxit < 1 || max_outer < 1) return fail(BCG_EINVAL, "inner_maxit and max_outer must be >= 1");
   h->precision = mode;
@@ -833,14 +969,16 @@ int bcg_solve(bcg_handle* h, const double* B, double* X, double tol, int maxit) 
   }
   if (h->sell)
     launch_sell_values(h->sell_slots, h->sl_map, h->vals, h->vals32, h->sl_val, h->sl_val32, h->stream);
-  int rc = h->precision == BCG_FP32_REFINE ? solve_refine(h, Bsolve, X, tol, maxit)
-                                           : solve_fp64(h, Bsolve, X, tol, maxit, nullptr, &its);
+  int rc = h->precision == BCG_FP32_REFINE     ? solve_refine(h, Bsolve, X, tol, maxit)
+           : h->precision == BCG_FP32_RELIABLE ? solve_reliable(h, Bsolve, X, tol, maxit)
+                                               : solve_fp64(h, Bsolve, X, tol, maxit, nullptr, &its);
   if (jac) {
     std::swap(h->vals, h->vals_s);
     std::swap(h->vals32, h->vals32_s);
     launch_scale_rows(h->n, h->k, X, h->dscale, X, 0, h->stream);  // X = D^{-1/2} Y
   }
-  if (h->precision != BCG_FP32_REFINE) h->info.iterations = its;
+  const bool mixed = h->precision == BCG_FP32_REFINE || h->precision == BCG_FP32_RELIABLE;
+  if (!mixed) h->info.iterations = its;
   const hipError_t se = hipStreamSynchronize(h->stream);
   if (se != hipSuccess && rc >= 0) rc = fail(BCG_EHIP, "solve failed: %s", hipGetErrorString(se));
   if (h->prof_on) prof_collect(h, 0);  // set-up launches still pending
@@ -854,7 +992,7 @@ int bcg_solve(bcg_handle* h, const double* B, double* X, double tol, int maxit) 
   double m = 0.0;
   for (double v : h->host_ratios) m = std::max(m, v);
   h->info.max_rel_res = m;
-  if (h->precision == BCG_FP32_REFINE) h->info.max_rel_res = h->info.true_rel_res;
+  if (mixed) h->info.max_rel_res = h->info.true_rel_res;
   h->info.status = rc;
   h->info.converged = rc == BCG_OK;
   h->info.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

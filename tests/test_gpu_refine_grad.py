@@ -91,6 +91,68 @@ def test_fp32_inner_iterations_match_oracle(monkeypatch, k, variant, p, path):
     assert err <= 1e-4
 
 
+RELIABLE_CASES = [(16, "block", 0), (16, "hybrid", 4), (16, "parallel", 1), (32, "block", 0), (64, "hybrid", 32),
+                  (48, "hybrid", 16), (8, "hybrid", 4), (12, "hybrid", 3), (128, "hybrid", 16), (64, "block", 0),
+                  (32, "global", 2)]
+
+
+@pytest.mark.parametrize("path", ["default", "no_mfma"])
+@pytest.mark.parametrize("k,variant,p", RELIABLE_CASES)
+def test_reliable_corrections_match_oracle(monkeypatch, k, variant, p, path):
+    """Residual replacement (delta = 0.1) against the oracle's scheme down to
+    tol 1e-3: three FP64 corrections within a few dozen FP32 iterations, each
+    resuming the same search direction. Both sides run the same FP32 policy up
+    to the rounding order of the FP32 sums; the correction counts must agree,
+    the iteration counts to within one (a threshold reached one iteration
+    apart after FP32 rounding-order differences; measured: equal in 21 of 22
+    cases, one apart for global(2)), and the solutions to 5e-4 per column
+    (measured 1e-5 to 2.1e-4; the FP32 and FP64 policies of the oracle differ
+    by 5e-5 to 2.3e-4 here). Planted in the
+    oracle, a line-6 product rescaled by s/s' instead of (s/s')^2, a
+    direction left unscaled or a restart change the iteration count by 12 to
+    over 3000 (from 26 to 46, 45 and 3734 for k = 16 block)."""
+    if path == "no_mfma":
+        monkeypatch.setenv("BCG_NO_MFMA", "1")
+    from oracle import refine
+    P = _P()
+    A = stencil_csr(2, 27, cell_coefficients(2, 27, 0.6))
+    B = rhs(A.shape[0], k, "normal", seed=140 + k)
+    Xo, io = refine.solve_reliable(A, B, variant, p, tol=1e-3, delta=0.1)
+    s = P.BCG(*csr_to_dev(A), k=k, subalgebra=variant, p=p)
+    s.set_precision("fp32_reliable", inner_tol=0.1, inner_maxit=1000, max_outer=50)
+    X, info = s.solve(dev(B), tol=1e-3)
+    err = rel(host(X), Xo)
+    log(f"reliable k={k} {variant} p={p} {path}: corrections {info['outer_iterations']}/{io['replacements']} "
+        f"iterations {info['iterations']}/{io['iterations']} rel {err:.3e}")
+    assert info["status"] == io["status"] == oracle.OK
+    assert info["fp64_fallback"] == 0 and not io["fp64_fallback"]
+    assert info["outer_iterations"] == io["replacements"] >= 3
+    assert abs(info["iterations"] - io["iterations"]) <= 1
+    assert err <= 5e-4
+
+
+@pytest.mark.parametrize("k,variant,p", [(16, "block", 0), (32, "block", 0), (64, "hybrid", 16), (8, "parallel", 1),
+                                         (64, "block", 0)])
+@pytest.mark.parametrize("delta", [0.0, 0.1])
+def test_reliable_converges_to_fp64_accuracy(k, variant, p, delta):
+    """Residual replacement to 1e-10: the true residual (recomputed on the
+    host) meets the tolerance, and the solution agrees with the plain FP64
+    solve to the accuracy both reach."""
+    P = _P()
+    A = stencil_csr(2, 48, cell_coefficients(2, 48, 0.8))
+    B = rhs(A.shape[0], k, "normal", seed=150 + k)
+    s = P.BCG(*csr_to_dev(A), k=k, subalgebra=variant, p=p)
+    s.set_precision("fp32_reliable", inner_tol=delta)
+    X, info = s.solve(dev(B), tol=1e-10)
+    s.set_precision("fp64")
+    X64, i64 = s.solve(dev(B), tol=1e-10)
+    log(f"reliable k={k} {variant} p={p} delta={delta}: {info['iterations']} FP32 iterations, "
+        f"{info['outer_iterations']} corrections; FP64 {i64['iterations']}")
+    assert info["status"] == oracle.OK and info["fp64_fallback"] == 0
+    assert _true_ratio(A, B, host(X)) <= 1e-10
+    assert rel(host(X), host(X64)) <= 1e-7
+
+
 def test_refine_stagnation_falls_back_to_fp64():
     # an inner tolerance too loose to halve the residual per outer step
     P = _P()

@@ -171,3 +171,44 @@ def test_refine_policy_mutation_is_caught(monkeypatch, mutation):
     assert fails, mutation
     # the whole-iteration pin catches both on its own
     assert "iterations" in fails
+
+
+# ---- residual replacement of the reliable refinement oracle (tests/test_oracle_reliable.py) ----
+from tests import test_oracle_reliable as rel_pins  # noqa: E402
+
+
+def _rescale_rho_linear(P, rho_old, f, policy32):
+    # the line-6 product scaled like one operand only
+    P = (P * np.float32(f)).astype(np.float32) if policy32 else P * f
+    return P, rho_old * f
+
+
+def _rescale_direction_kept(P, rho_old, f, policy32):
+    # the search direction left in the old units
+    return P, rho_old * (f * f)
+
+
+def _rescale_restart(P, rho_old, f, policy32):
+    # a restart in place of the continued direction: with P = 0 the next
+    # line 13 gives P = R
+    return np.zeros_like(P), rho_old * (f * f)
+
+
+def _reliable_pin_fails(variant, p):
+    try:
+        err, ir, its64 = rel_pins.reliable_fp64_mismatch(variant, p, maxit=1000)
+    except Exception:  # a breakdown is a failure of the pin too
+        return True
+    return not (ir["status"] == 0 and abs(ir["iterations"] - its64) <= 2 and err <= 1e-8)
+
+
+def test_reliable_unmutated_passes():
+    assert not _reliable_pin_fails("block", 0)
+    assert not _reliable_pin_fails("parallel", 1)
+
+
+@pytest.mark.parametrize("mutation", [_rescale_rho_linear, _rescale_direction_kept, _rescale_restart])
+@pytest.mark.parametrize("variant,p", [("block", 0), ("parallel", 1), ("hybrid", 2)])
+def test_reliable_mutation_is_caught(monkeypatch, mutation, variant, p):
+    monkeypatch.setattr(orf, "_rescale_direction", mutation)
+    assert _reliable_pin_fails(variant, p)
