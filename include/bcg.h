@@ -180,6 +180,34 @@ int bcg_set_precision(bcg_handle *h, int mode, double inner_tol, int inner_maxit
  */
 int bcg_solve(bcg_handle *h, const double *B, double *X, double tol, int maxit);
 
+/*
+ * bcg_solve_noalloc -- bcg_create + bcg_solve (FP64, M = I, natural row
+ * order) + bcg_destroy in one call that allocates no memory: for callers
+ * that cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). Arguments as bcg_create and bcg_solve;
+ * hip_stream as bcg_set_stream; info (host, may be NULL) receives what
+ * bcg_get_info would report.
+ *   - The matrix is read in place from the caller's arrays (not copied);
+ *     its contents are checked on the device first, as bcg_create does.
+ *   - Every workspace buffer of the solve (residual, search directions,
+ *     products, reduction partials, coefficients, device state) lives in
+ *     one fixed array of 128 MiB that each GPU the library runs on holds
+ *     until the process ends. A solve whose workspace (3 n k doubles plus
+ *     the partial products) exceeds it returns BCG_EINVAL with a message;
+ *     bcg_create then serves it.
+ *   - The array keeps the last call's contents: each call resets the
+ *     device state it reads. Calls that overlap on one GPU (other threads,
+ *     other streams) share the array and race; the caller serialises them.
+ *   - Results equal bcg_solve's for the same inputs (same kernels, same
+ *     launch plan). The solve reads its state back synchronously after each
+ *     chunk of iterations (no pinned memory or events), so it can be slower
+ *     than a handle's solve on long iteration counts.
+ * Returns as bcg_solve, and BCG_EINVAL for malformed CSR, k, subalgebra or
+ * p, or a workspace beyond the fixed array.
+ */
+int bcg_solve_noalloc(const bcg_csr *A, int k, int subalgebra, int p, const double *B, double *X, double tol,
+                      int maxit, void *hip_stream, bcg_info *info);
+
 /* Copies new matrix values (same pattern as at create; device array of nnz
  * FP64) into the handle, e.g. for a differentiable solve. Stream-ordered;
  * with the Jacobi preconditioner on, also recomputes its scaling and waits

@@ -55,6 +55,9 @@ SIGNATURES = [
                                          ctypes.c_int]),
     ("bcg_solve", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                  ctypes.c_int]),
+    ("bcg_solve_noalloc", ctypes.c_int, [ctypes.POINTER(Csr), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
+                                         ctypes.c_void_p, ctypes.POINTER(Info)]),
     ("bcg_update_values", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("bcg_set_preconditioner", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("bcg_csr_outer", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,

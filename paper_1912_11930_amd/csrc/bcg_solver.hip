@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -225,6 +226,11 @@ int reset_state(bcg_handle* h) {
 }
 
 int read_state(bcg_handle* h, DevState* out) {
+  if (!h->st_host) {  // a handle without pinned state slots (the allocation-free solve)
+    HIP_TRY(hipMemcpyAsync(out, h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return BCG_OK;
+  }
   HIP_TRY(hipMemcpyAsync(h->st_host, h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   *out = h->st_host[0];
@@ -339,6 +345,28 @@ int run_iterations(bcg_handle* h, const IterBuffers<T>& b, double tol, int maxit
   };
   const int first = std::min(h->chunk, 8);
   int rc;
+  if (!h->st_host) {
+    // no pinned state slots or events (the allocation-free solve): one chunk
+    // at a time, its state read back synchronously
+    int want = first;
+    while (enq < maxit) {
+      const int c = std::min(want, maxit - enq);
+      for (int j = 0; j < c; ++j) enqueue_iteration<T>(h, b, tol, enq + 1 + j, maxit);
+      enq += c;
+      HIP_TRY(hipGetLastError());
+      DevState seen{};
+      if ((rc = read_state(h, &seen))) return rc;
+      if (seen.done || seen.last) break;
+      it_a = it_b;
+      r_a = r_b;
+      it_b = seen.iter;
+      r_b = seen.max_ratio;
+      want = next_chunk(h, tol, enq, it_a, r_a, it_b, r_b);
+    }
+    rc = read_state(h, final_state);
+    if (h->prof_on) prof_collect(h, final_state->iter);
+    return rc;
+  }
   if (maxit > 0) {
     if ((rc = enqueue_chunk(0, first))) return rc;
     inflight = 1;
@@ -821,9 +849,148 @@ int validate_p(int variant, int k, int p, int* p_out) {
 
 }  // namespace
 
+// Workspace of bcg_solve_noalloc: one array per GPU the library runs on,
+// held until the process ends. Host code never uses its name as an address:
+// each device's copy is reached through the pointer hipGetSymbolAddress
+// returns for that device.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's scratch array (looked up once per device).
+int scratch_address(int device, unsigned char** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(BCG_EINVAL, "device %d outside 0..%d", device, kMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+      return fail(BCG_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", device, hipGetErrorString(e));
+    g_scratch_ptr[device] = static_cast<unsigned char*>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return BCG_OK;
+}
+
+// Consecutive 256-byte aligned slices of the scratch array (base nullptr:
+// only the total is counted).
+struct Carve {
+  unsigned char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += (count ? count : 1) * sizeof(T);
+    return p;
+  }
+};
+
+// Points every workspace buffer of an FP64 solve into `c` (as bcg_create
+// sizes them; the matrix stays the caller's).
+void carve_workspace(bcg_handle& h, Carve& c) {
+  const Plan& pl = h.pl;
+  const size_t nk = static_cast<size_t>(h.n) * h.k;
+  h.R = c.take<double>(nk);
+  h.P = c.take<double>(nk);
+  h.Q = c.take<double>(nk);
+  h.partA = c.take<double>(static_cast<size_t>(std::max({pl.nwg, pl.sp_nwg[0], pl.sp_nwg[1]})) * pl.W);
+  h.part2 = c.take<double>(static_cast<size_t>(kRedSplits) * pl.W);
+  h.partR = c.take<double>(static_cast<size_t>(pl.nwg) * pl.W);
+  h.partN = c.take<double>(static_cast<size_t>(pl.nwg) * pl.W);
+  h.alpha = c.take<double>(pl.W);
+  h.rho = c.take<double>(pl.W);
+  h.rnew = c.take<double>(pl.W);
+  h.lam = c.take<double>(pl.E);
+  h.beta = c.take<double>(pl.E);
+  h.lam32 = c.take<float>(pl.E);
+  h.beta32 = c.take<float>(pl.E);
+  h.ws = c.take<double>(pl.p > 48 ? static_cast<size_t>(pl.qo) * 2 * pl.p * pl.p : 1);
+  h.r0 = c.take<double>(h.k);
+  h.ratios = c.take<double>(h.k);
+  h.scale = c.take<double>(1);
+  h.st = c.take<DevState>(1);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* bcg_last_error(void) { return g_error.c_str(); }
+
+int bcg_solve_noalloc(const bcg_csr* A, int k, int subalgebra, int p, const double* B, double* X, double tol,
+                      int maxit, void* hip_stream, bcg_info* info) {
+  g_error.clear();
+  if (!A || !A->rowptr || !A->colind || !A->values) return fail(BCG_EINVAL, "CSR arrays must be non-NULL");
+  if (A->n < 1 || A->n >= INT32_MAX || A->nnz < 0 || A->nnz >= INT32_MAX)
+    return fail(BCG_EINVAL, "n=%lld nnz=%lld outside the int32 index range", (long long)A->n, (long long)A->nnz);
+  if (!B || !X || static_cast<const void*>(B) == static_cast<const void*>(X))
+    return fail(BCG_EINVAL, "B and X must be distinct non-NULL device arrays");
+  if (!(tol >= 0.0) || !std::isfinite(tol) || maxit < 0) return fail(BCG_EINVAL, "tol must be finite >= 0, maxit >= 0");
+  int pn = 0;
+  int rc = validate_p(subalgebra, k, p, &pn);
+  if (rc) return rc;
+  const auto t0 = std::chrono::steady_clock::now();
+  bcg_handle h;
+  h.n = A->n;
+  h.nnz = A->nnz;
+  h.k = k;
+  h.p = pn;
+  h.variant = subalgebra;
+  const int dec = pn == 1 && (subalgebra == BCG_PARALLEL || subalgebra == BCG_HYBRID);
+  h.pl = make_plan(h.n, h.nnz, k, pn, subalgebra == BCG_GLOBAL ? 1 : 0, dec);
+  Carve need{nullptr};
+  carve_workspace(h, need);
+  if (need.off > kScratchBytes)
+    return fail(BCG_EINVAL, "the solve needs %zu bytes of workspace; bcg_solve_noalloc holds %zu (use bcg_create)",
+                need.off, kScratchBytes);
+  HIP_TRY(hipGetDevice(&h.device));
+  unsigned char* base = nullptr;
+  if ((rc = scratch_address(h.device, &base))) return rc;
+  Carve c{base};
+  carve_workspace(h, c);
+  h.stream = static_cast<hipStream_t>(hip_stream);
+  // the caller's matrix is read in place (the kernels never write it)
+  h.rowptr = const_cast<int32_t*>(A->rowptr);
+  h.colind = const_cast<int32_t*>(A->colind);
+  h.vals = const_cast<double*>(A->values);
+  h.host_ratios.assign(k, 1.0);
+  // the CSR contents, before any kernel follows a row range
+  if ((rc = reset_state(&h))) return rc;
+  launch_check_csr(h.rowptr, h.colind, h.n, h.nnz, &h.st->status, h.stream);
+  HIP_TRY(hipGetLastError());
+  DevState chk{};
+  if ((rc = read_state(&h, &chk))) return rc;
+  if (chk.status != 0)
+    return fail(BCG_EINVAL, "malformed CSR: needs rowptr[0] = 0, rowptr non-decreasing, rowptr[n] = nnz "
+                            "and every column index in [0, n)");
+  h.info = bcg_info{};
+  h.info.k = k;
+  int its = 0;
+  rc = solve_fp64(&h, B, X, tol, maxit, nullptr, &its);
+  h.info.iterations = its;
+  const hipError_t se = hipStreamSynchronize(h.stream);
+  if (se != hipSuccess && rc >= 0) rc = fail(BCG_EHIP, "solve failed: %s", hipGetErrorString(se));
+  if (rc != BCG_EINVAL && rc != BCG_EHIP && (int)h.ref_r0.size() == k) {
+    launch_residual(h.pl, h.rowptr, h.colind, h.vals, B, X, h.Q, nullptr, h.partN, 0, h.stream);
+    launch_reduce(h.pl, h.partN, h.rnew, h.pl.W, nullptr, h.stream);
+    std::vector<double> n2;
+    if (fetch_norms(&h, h.rnew, n2) == BCG_OK) h.info.true_rel_res = max_ratio(n2, h.ref_r0);
+  }
+  double m = 0.0;
+  for (double v : h.host_ratios) m = std::max(m, v);
+  h.info.max_rel_res = m;
+  h.info.status = rc;
+  h.info.converged = rc == BCG_OK;
+  h.info.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = h.info;
+  return rc;
+}
 
 int bcg_create(const bcg_csr* A, int k, int subalgebra, int p, bcg_handle** out) {
   g_error.clear();

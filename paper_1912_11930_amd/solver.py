@@ -169,6 +169,35 @@ class BCG:
             pass
 
 
+def solve_noalloc(rowptr: torch.Tensor, colind: torch.Tensor, values: torch.Tensor, B: torch.Tensor,
+                  X: torch.Tensor, subalgebra: str = "block", p: int = 0, tol: float = 1e-8,
+                  maxit: int = 10000) -> dict:
+    """FP64 solve of A X = B in place of X (X holds the initial guess) that
+    allocates no device memory: its workspace is the library's fixed per-GPU
+    array (bcg_solve_noalloc). Returns the info dict of the solve."""
+    n, nnz = rowptr.numel() - 1, colind.numel()
+    _require(rowptr, "rowptr", torch.int32, (n + 1,))
+    _require(colind, "colind", torch.int32, (nnz,))
+    _require(values, "values", torch.float64, (nnz,))
+    if B.dim() != 2:
+        raise BCGError(_capi.BCG_EINVAL, "B must be n x k")
+    k = B.shape[1]
+    _require(B, "B", torch.float64, (n, k))
+    _require(X, "X", torch.float64, (n, k))
+    if subalgebra not in _capi.SUBALGEBRA:
+        raise BCGError(_capi.BCG_EINVAL, f"unknown subalgebra {subalgebra!r}")
+    csr = _capi.Csr(n, nnz, rowptr.data_ptr(), colind.data_ptr(), values.data_ptr())
+    inf = _capi.Info()
+    with torch.cuda.device(B.device):
+        status = check(_capi.lib().bcg_solve_noalloc(ctypes.byref(csr), k, _capi.SUBALGEBRA[subalgebra], p,
+                                                     B.data_ptr(), X.data_ptr(), float(tol), int(maxit),
+                                                     _stream_ptr(B.device), ctypes.byref(inf)))
+    d = inf.as_dict()
+    d["status"] = status
+    d["status_name"] = _capi.STATUS_NAME.get(status, str(status))
+    return d
+
+
 def stencil_nnz(dim: int, N: int) -> int:
     nnz = _capi.lib().bcg_stencil_nnz(dim, N)
     if nnz < 0:

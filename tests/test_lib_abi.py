@@ -61,3 +61,19 @@ def test_argument_validation_without_device(lib):
     assert lib.bcg_set_sell(None, 1, 1) == _capi.BCG_EINVAL
     assert lib.bcg_stencil_build(4, 8, None, None, None, None, None) == _capi.BCG_EINVAL
     lib.bcg_destroy(None)
+
+
+def test_noalloc_argument_validation_without_device(lib):
+    # every rejection below happens on the host, before the fixed array is touched
+    from paper_1912_11930_amd import _capi
+    EINVAL = _capi.BCG_EINVAL
+    f = lib.bcg_solve_noalloc
+    assert f(None, 8, 0, 0, 4, 5, 1e-8, 10, None, None) == EINVAL
+    csr = _capi.Csr(16, 64, 1, 2, 3)
+    assert f(ctypes.byref(csr), 8, 0, 0, None, 5, 1e-8, 10, None, None) == EINVAL      # B NULL
+    assert f(ctypes.byref(csr), 8, 0, 0, 4, 4, 1e-8, 10, None, None) == EINVAL        # B aliases X
+    assert f(ctypes.byref(csr), 8, 0, 0, 4, 5, -1.0, 10, None, None) == EINVAL        # tol < 0
+    assert f(ctypes.byref(csr), 8, 3, 3, 4, 5, 1e-8, 10, None, None) == EINVAL        # p does not divide k
+    big = _capi.Csr(10_000_000, 70_000_000, 1, 2, 3)                                  # 3 n k doubles > 128 MiB
+    assert f(ctypes.byref(big), 8, 0, 0, 4, 5, 1e-8, 10, None, None) == EINVAL
+    assert b"workspace" in lib.bcg_last_error()
