@@ -3,9 +3,10 @@
 A step is one complete solve A X = B from X = 0 to the stop rule (every
 column's residual reduced by 1e-8) of the synthetic 3D 7-point Poisson
 system on a 256^3 grid (n = 16,777,216) with k = 128 uniform right-hand
-sides, hybrid subalgebra with p = 16, in the FP32 + FP64-refinement form,
-with every kernel of the iteration on the GPU and B, X, A resident in HBM
-before the timed region. value = k * steps / wall time.
+sides, hybrid subalgebra with p = 16, in the FP32 + FP64-refinement form
+(FP32 block CG whose search direction is kept across FP64 corrections by
+residual replacement), with every kernel of the iteration on the GPU and B,
+X, A resident in HBM before the timed region. value = k * steps / wall time.
 
 Also reported on the same JSON line:
   compare       the plain FP64 solve of the same system (its rate, the
@@ -45,7 +46,7 @@ def log(msg: str) -> None:
 
 def algorithmic_bytes(cls: str, n: int, nnz: int, k: int, precision: str) -> float:
     """Bytes one launch of a kernel class must move (each operand once)."""
-    vb = 4 if precision == "fp32_refine" else 8
+    vb = 8 if precision == "fp64" else 4
     if cls == "spmm":            # A (values + column index + row pointer), P read, Q written
         return vb * nnz + 4 * nnz + 4 * (n + 1) + 2 * vb * n * k
     if cls == "update_r":        # Q, R read; R written
@@ -74,13 +75,18 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def data_type(precision: str) -> str:
+    """Element type of the row kernels: fp64, or fp32 for both mixed forms."""
+    return "fp64" if precision == "fp64" else "fp32"
+
+
 def measured_traffic(kernel: str, workload: str, variant: str, precision: str):
     """HBM bytes per launch from committed rocprofv3 counter runs, if current."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path))[f"{kernel}/{workload}/{variant}/{precision}"]
+        rec = json.load(open(path))[f"{kernel}/{workload}/{variant}/{data_type(precision)}"]
     except (KeyError, ValueError):
         return None
     if rec.get("kernel_hash") != kernel_hash():
@@ -150,7 +156,7 @@ def traffic_from(directory: str, workload: str, variant: str) -> int:
     write = _pmc_means(db("write"), "WRITE_SIZE")
     path = os.path.join(ROOT, "profiles", "traffic.json")
     rec = json.load(open(path)) if os.path.exists(path) else {}
-    for precision in ("fp64", "fp32_refine"):
+    for precision in ("fp64", "fp32"):
         want32 = precision != "fp64"
         for cls, knames in KERNEL_NAMES.items():
             def pick(table):
@@ -263,16 +269,19 @@ def main() -> int:
     ap.add_argument("--budget-s", type=float, default=420.0,
                     help="wall-time budget (s) past which the optional variant solves are skipped")
     ap.add_argument("--no-variants", action="store_true", help="skip the other subalgebras of the workload")
-    ap.add_argument("--precision", default="fp32_refine", choices=["fp64", "fp32_refine"],
-                    help="precision of the headline solve; the other form is timed beside it")
+    ap.add_argument("--precision", default="fp32_reliable", choices=["fp64", "fp32_refine", "fp32_reliable"],
+                    help="form of the headline solve: FP32 with FP64 refinement by residual replacement "
+                         "(fp32_reliable) or by restarted inner solves (fp32_refine), or plain FP64; the plain "
+                         "FP64 form (FP32 with residual replacement when the headline is FP64) is timed beside it")
     ap.add_argument("--no-compare", action="store_true", help="skip the solve in the other precision")
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precond", default="none", choices=["none", "jacobi"],
                     help="preconditioner M of Algorithm 1 (jacobi: M = diag(A))")
-    ap.add_argument("--schedule", default="tiled", choices=["tiled", "natural"],
-                    help="row order of the sparse product: 32x32 x-y tiles swept through z (3D), or natural")
+    ap.add_argument("--schedule", default="bricks", choices=["bricks", "tiled", "natural"],
+                    help="row order of the sparse product (3D): 4x2x2 bricks inside 16x32x2 tiles swept "
+                         "through z (bricks), 32x32 x-y tiles swept through z (tiled), or natural")
     ap.add_argument("--sell", type=int, default=0, metavar="SIGMA",
                     help="sparse product on SELL-16-SIGMA storage (SIGMA 1 or a multiple of 16; 0: CSR)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -328,6 +337,9 @@ def main() -> int:
     if args.schedule == "tiled" and w.dim == 3:
         order = P.stencil_schedule(w.dim, w.N, 32, device=dev)
         schedule = "tiled 32x32 (x,y) swept through z"
+    elif args.schedule == "bricks" and w.dim == 3:
+        order = P.stencil_brick_schedule(w.N, (16, 32, 2), (4, 2, 2), device=dev)
+        schedule = "4x2x2 bricks in 16x32x2 tiles swept through z"
 
     def make_solver(variant: str, p: int):
         sv = P.BCG(rp, ci, va, k=k, subalgebra=variant, p=p)
@@ -430,7 +442,7 @@ def main() -> int:
         "cpu_baseline": None,
     }
     if not args.no_compare:
-        other = "fp64" if args.precision != "fp64" else "fp32_refine"
+        other = "fp64" if args.precision != "fp64" else "fp32_reliable"
         cmp_ = run(other, args.compare_steps, 1)
         diff = float(torch.linalg.norm(head["X"] - cmp_["X"]) / torch.linalg.norm(cmp_["X"]))
         cs = args.compare_steps
@@ -486,7 +498,7 @@ def variant_solves(args, w, tol, B, make_solver, t_start: float, out: dict) -> l
         sv = make_solver(variant, p)
         X = torch.empty_like(B)
         rec = {"variant": variant, "p": p}
-        for precision in (args.precision, "fp64" if args.precision != "fp64" else "fp32_refine"):
+        for precision in (args.precision, "fp64" if args.precision != "fp64" else "fp32_reliable"):
             sv.set_precision(precision)
             X.zero_()
             sv.solve(B, X, tol=tol, maxit=100000)

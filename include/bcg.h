@@ -373,6 +373,18 @@ int bcg_stencil_build(int dim, int N, const double *kappa, int32_t *rowptr, int3
  * int32[N^dim]. Stream-ordered. */
 int bcg_stencil_schedule(int dim, int N, int tile, int32_t *order, void *hip_stream);
 
+/* Brick row schedule of the 3D stencil on an N^3 grid (not in the paper: a
+ * cache-locality order for wide blocks, where a row of P spans several
+ * cache lines): tiles of tile[0] x tile[1] x tile[2] cells (x, y, z) visited
+ * tile column by tile column (row-major over the tiles' y, x) and each
+ * column swept through z; inside a tile, bricks of brick[0] x brick[1] x
+ * brick[2] cells with x fastest, then y, then z; inside a brick x fastest.
+ * A 16-row step of the sparse product is then a compact brick, so fewer
+ * distinct neighbour rows are gathered per step. tile, brick: host int[3]
+ * with brick[d] | tile[d] | N. order: device int32[N^3], position -> row.
+ * Returns BCG_EINVAL for other sizes. Stream-ordered. */
+int bcg_stencil_brick_schedule(int N, const int *tile, const int *brick, int32_t *order, void *hip_stream);
+
 /* Transpose Jacobian of the stencil values with respect to kappa:
  * dkappa[c] = sum_e dvalues[e] * d values[e] / d kappa[c] (device arrays;
  * dvalues in the CSR order of bcg_stencil_build). Stream-ordered. */

@@ -7,4 +7,5 @@ kernels for gfx950 behind the C ABI of include/bcg.h.
 """
 from ._capi import BCGError, LIB_PATH  # noqa: F401
 from .autograd import BCGSolve, StencilValues  # noqa: F401
-from .solver import BCG, solve_noalloc, stencil, stencil_kappa_vjp, stencil_nnz, stencil_schedule  # noqa: F401
+from .solver import (BCG, solve_noalloc, stencil, stencil_brick_schedule, stencil_kappa_vjp,  # noqa: F401
+                     stencil_nnz, stencil_schedule)

@@ -77,6 +77,8 @@ SIGNATURES = [
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     ("bcg_stencil_schedule", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                             ctypes.c_void_p]),
+    ("bcg_stencil_brick_schedule", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                                  ctypes.POINTER(ctypes.c_int), ctypes.c_void_p, ctypes.c_void_p]),
     ("bcg_stencil_kappa_vjp", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p]),
 ]

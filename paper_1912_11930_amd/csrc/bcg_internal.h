@@ -68,6 +68,9 @@ struct Plan {
   int sp_o32[2];  // sparse product with 32-bit lane offsets (FP64, FP32)
   int nt[2];      // row kernels stream dead operands non-temporally (FP64, FP32)
   int ugw[2];     // column groups per wave of the matrix-core update passes (FP64, FP32)
+  // matrix-core plan whose R update (bit 0) / X-P pass (bit 1) run on the
+  // k-specialised vector kernels instead (FP64, FP32)
+  int upd_vec[2];
   const int32_t* sched;  // processing order of the sparse-product rows (nullptr: natural)
   int sell;     // 1: the matrix-core sparse product reads SELL-16-sigma storage
                 // (rowptr: slice starts, sched: position -> row)

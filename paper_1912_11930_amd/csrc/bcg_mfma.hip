@@ -1452,7 +1452,7 @@ void check_grid(const Plan& pl, int w) {
 // set of index loads, where two waves of 16 columns each load them twice.
 // Measured 5-24 % faster for k = 32..128.
 int mfma_sp_width(int k, int w, int p) {
-  if (w == 16 && k % 32 == 0 && 32 % p == 0) return 32;
+  if (w == 16 && k % 32 == 0 && 32 % p == 0 && !env_set("BCG_SP_W16")) return 32;
   return w;
 }
 
@@ -1482,6 +1482,10 @@ void mfma_sp_grid(Plan& pl) {
     const int need = std::max(static_cast<int>(std::ceil(256.0 * pl.W / step_bytes)), 1024 / (wpg * rows_step));
     int chunk = 1;
     while (chunk < need) chunk *= 2;
+    if (const char* e = std::getenv("BCG_SP_CHUNK")) {  // override (a power of two)
+      const int v = std::atoi(e);
+      if (v > 0 && (v & (v - 1)) == 0) chunk = v;
+    }
     const int64_t per = (nsteps + 7) / 8;
     int64_t span = static_cast<int64_t>(chunk) * wpg, nch = (per + span - 1) / span;
     while (8 * ngb * nch > kMaxSpWG) {
@@ -1511,6 +1515,20 @@ void mfma_sp_grid(Plan& pl) {
       if ((v == 1 || v == 2) && ng % v == 0 && (v == 1 || pl.mfma == 16)) gw = v;
     }
     pl.ugw[prec] = gw;
+    // vector update passes beside the matrix-core sparse product where they
+    // measured faster on the 256^3, k = 128 Poisson workload: FP32 R update
+    // and X/P pass for p <= 8 (5.0 against 5.4 ms and 8.0 against 9.2 ms at
+    // p = 8; 4.9 / 5.4 and 7.2 / 8.5 ms at p = 1), the FP64 R update for
+    // p <= 16 (9.5 against 10.4 ms at p = 16); k = 16 is faster on the matrix
+    // cores throughout. BCG_UPDATE_VEC32 / BCG_UPDATE_VEC64 = 0..3 override
+    // (bit 0: R update, bit 1: X/P pass).
+    int vec = 0;
+    if (pl.fast && pl.k == 128) vec = prec ? (pl.p <= 8 ? 3 : 0) : 1;
+    if (const char* e = std::getenv(prec ? "BCG_UPDATE_VEC32" : "BCG_UPDATE_VEC64")) {
+      const int v = std::atoi(e);
+      if (v >= 0 && v <= 3) vec = pl.fast ? v : 0;
+    }
+    pl.upd_vec[prec] = vec;
   }
 }
 

@@ -254,8 +254,9 @@ void enqueue_update_xp(bcg_handle* h, const IterBuffers<T>& b, int it) {
   const Plan& pl = h->pl;
   hipStream_t s = h->stream;
   const bool mfma = h->path == RowPath::mfma, fast = mfma || h->path == RowPath::fast;
+  const bool vec = mfma && (pl.upd_vec[std::is_same<T, float>::value ? 1 : 0] & 2);
   timed(h, BCG_K_UPDATE_XP, it, [&] {
-    if (mfma)
+    if (mfma && !vec)
       launch_update_xp_mfma<T>(pl, b.X, b.P, b.R, b.lam, b.beta, h->partR, h->st, s);
     else if (fast)
       launch_update_xp_fast<T>(pl, b.X, b.P, b.R, b.lam, b.beta, h->partR, h->st, s);
@@ -295,8 +296,9 @@ void enqueue_iteration(bcg_handle* h, const IterBuffers<T>& b, double tol, int i
     launch_reduce_lambda(pl, h->partA, sp_rows, h->part2, h->partR, it > 1 ? pl.nwg : 0, h->alpha, h->rho, h->lam,
                          h->lam32, h->ws, h->st, s);
   });
+  const bool vec = mfma && (pl.upd_vec[std::is_same<T, float>::value ? 1 : 0] & 1);
   timed(h, BCG_K_UPDATE_R, it, [&] {  // line 9 and the product of line 11
-    if (mfma)
+    if (mfma && !vec)
       launch_update_r_mfma<T>(pl, b.R, b.Q, b.lam, h->partN, h->st, s);
     else if (fast)
       launch_update_r_fast<T>(pl, b.R, b.Q, b.lam, h->partN, h->st, s);

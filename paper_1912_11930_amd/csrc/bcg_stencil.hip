@@ -172,6 +172,26 @@ __global__ __launch_bounds__(kThreads) void k_schedule(Grid g, int T, int32_t* _
   }
 }
 
+// Brick order of the 3D grid: tiles of tx x ty x tz cells, visited tile
+// column by tile column (row-major over (ty, tx)), each column swept through
+// z; inside a tile, bricks of bx x by x bz cells with x fastest, then y, then
+// z; inside a brick, cells with x fastest. Position e -> row.
+struct Bricks {
+  int tx, ty, tz, bx, by, bz;
+};
+__global__ __launch_bounds__(kThreads) void k_brick_schedule(int64_t N, Bricks b, int32_t* __restrict__ order) {
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= N * N * N) return;
+  const int64_t tv = (int64_t)b.tx * b.ty * b.tz, bv = (int64_t)b.bx * b.by * b.bz;
+  const int64_t ntx = N / b.tx, ntz = N / b.tz, nbx = b.tx / b.bx, nby = b.ty / b.by;
+  const int64_t t = e / tv, in_t = e - t * tv, br = in_t / bv, c = in_t - br * bv;
+  const int64_t TZ = t % ntz, t2 = t / ntz, TX = t2 % ntx, TY = t2 / ntx;
+  const int64_t BX = br % nbx, br2 = br / nbx, BY = br2 % nby, BZ = br2 / nby;
+  const int64_t cx = c % b.bx, c2 = c / b.bx, cy = c2 % b.by, cz = c2 / b.by;
+  const int64_t x = TX * b.tx + BX * b.bx + cx, y = TY * b.ty + BY * b.by + cy, z = TZ * b.tz + BZ * b.bz + cz;
+  order[e] = static_cast<int32_t>(x + N * y + N * N * z);
+}
+
 bool make_grid(int dim, int N, Grid* g) {
   if ((dim != 2 && dim != 3) || N < 1) return false;
   g->dim = dim;
@@ -200,6 +220,18 @@ extern "C" int bcg_stencil_build(int dim, int N, const double* kappa, int32_t* r
   const int64_t blocks = (g.n + kThreads - 1) / kThreads;
   hipLaunchKernelGGL(k_build, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0,
                      static_cast<hipStream_t>(hip_stream), g, kappa, rowptr, colind, values);
+  return hipGetLastError() == hipSuccess ? BCG_OK : BCG_EHIP;
+}
+
+extern "C" int bcg_stencil_brick_schedule(int N, const int* tile, const int* brick, int32_t* order,
+                                          void* hip_stream) {
+  if (!tile || !brick || !order || N < 1 || static_cast<int64_t>(N) * N * N >= INT32_MAX) return BCG_EINVAL;
+  for (int d = 0; d < 3; ++d)
+    if (tile[d] < 1 || brick[d] < 1 || N % tile[d] != 0 || tile[d] % brick[d] != 0) return BCG_EINVAL;
+  const Bricks b{tile[0], tile[1], tile[2], brick[0], brick[1], brick[2]};
+  const int64_t n = static_cast<int64_t>(N) * N * N, blocks = (n + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(k_brick_schedule, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0,
+                     static_cast<hipStream_t>(hip_stream), static_cast<int64_t>(N), b, order);
   return hipGetLastError() == hipSuccess ? BCG_OK : BCG_EHIP;
 }
 

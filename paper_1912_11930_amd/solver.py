@@ -232,6 +232,17 @@ def stencil_schedule(dim: int, N: int, tile: int = 32, device="cuda") -> torch.T
     return order
 
 
+def stencil_brick_schedule(N: int, tile=(16, 32, 2), brick=(4, 2, 2), device="cuda") -> torch.Tensor:
+    """Brick row order of the 3D stencil on an N^3 grid (bcg_stencil_brick_schedule)."""
+    device = torch.device(device)
+    order = torch.empty(N ** 3, dtype=torch.int32, device=device)
+    t = (ctypes.c_int * 3)(*tile)
+    b = (ctypes.c_int * 3)(*brick)
+    with torch.cuda.device(device):
+        check(_capi.lib().bcg_stencil_brick_schedule(N, t, b, order.data_ptr(), _stream_ptr(device)))
+    return order
+
+
 def stencil_kappa_vjp(dim: int, N: int, kappa: torch.Tensor, dvalues: torch.Tensor) -> torch.Tensor:
     """dL/dkappa from dL/dvalues through the stencil assembly."""
     n = N ** dim

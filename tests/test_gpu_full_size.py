@@ -30,7 +30,6 @@ import oracle
 import os
 
 from oracle.bcg import solve as oracle_solve
-from oracle.grad import kappa_vjp as oracle_kappa_vjp, sampled_outer as oracle_sampled_outer
 from oracle.stencil import stencil_csr
 from tests.gpu_helpers import dev, host, log, rel
 from workload import WORKLOADS, cell_coefficients, coefficients_for, loss_weights, rhs, rhs_for
@@ -269,18 +268,21 @@ def test_diffusion3d_192_refinement_to_1e10(diffusion192, variant, p, precision)
 
 
 # ------------------------------------------ 512^2 diffusion, k = 32, gradient
-@pytest.mark.timeout(900)
+@pytest.mark.timeout(600)
 def test_diffusion2d_512_gradient_matches_oracle():
     """Forward solve and adjoint backward of L = sum(W * X) (block, FP64, tol
-    1e-12 on both sides) against the oracle's adjoint gradient at full size:
-    dL/dB = A^{-1} W per column to 1e-9; dL/dkappa per cell to 1e-8 of the
-    largest of |component| and 1e-3 of the gradient's largest component."""
+    1e-12) against the oracle's adjoint gradient at full size, stored by
+    ``tests/golden/make_diffusion2d_512_gradient_fixture.py`` (the oracle's
+    solves take minutes on the host): the same iteration counts; dL/dB =
+    A^{-1} W on 1024 sampled rows to 1e-9 per column; dL/dkappa on 4096
+    sampled cells to 1e-8 of the larger of |component| and 1e-3 of the
+    gradient's largest magnitude."""
     P = _P()
     w = WORKLOADS["diffusion2d_512_k32"]
     dim, N, k = w.dim, w.N, w.k
-    tol = 1e-12
+    ref = np.load(os.path.join(GOLDEN, "diffusion2d_512_k32_gradient.npz"))
+    tol = float(ref["tol"])
     kappa = cell_coefficients(dim, N, w.sigma)
-    A = stencil_csr(dim, N, kappa)
     B = rhs(w.n, k, w.rhs)
     W = loss_weights(w.n, k)
     log("512^2 k=32 block: adjoint gradient against the oracle's")
@@ -290,21 +292,22 @@ def test_diffusion2d_512_gradient_matches_oracle():
     s = P.BCG(rp, ci, v0, k=k, subalgebra="block")
     vals = P.StencilValues.apply(kt, dim, N)
     X = P.BCGSolve.apply(vals, Bt, s, tol, 100000)
+    its_fwd = s.info()["iterations"]
     (dev(W) * X).sum().backward()
-    gB, gk = host(Bt.grad), host(kt.grad)
-    def progress(name):
-        def cb(i, X_, R_):
-            if i % 100 == 0:
-                log(f"  oracle {name}: iteration {i}")
-        return cb
-
-    Xo, io = oracle_solve(A, B, "block", 0, tol=tol, maxit=100000, callback=progress("forward"))
-    Yo, iy = oracle_solve(A, W, "block", 0, tol=tol, maxit=100000, callback=progress("adjoint"))
-    assert io["status"] == iy["status"] == oracle.OK
-    dk = oracle_kappa_vjp(dim, N, kappa, A, oracle_sampled_outer(A, Yo, Xo, -1.0))
-    errB = rel(gB, Yo)
-    scale = np.maximum(np.abs(dk), 1e-3 * np.abs(dk).max())
-    errk = float(np.max(np.abs(gk - dk) / scale))
+    its_adj = s.info()["iterations"]
+    log(f"iterations gpu={its_fwd}/{its_adj} oracle={int(ref['iterations_forward'])}/{int(ref['iterations_adjoint'])}")
+    assert int(ref["status_forward"]) == int(ref["status_adjoint"]) == oracle.OK
+    # at 1e-12 the recursive residual is close to FP64's attainable accuracy,
+    # so rounding-order differences move the stop by a few iterations
+    # (measured: 721/719 against 723/720)
+    assert abs(its_fwd - int(ref["iterations_forward"])) <= 4
+    assert abs(its_adj - int(ref["iterations_adjoint"])) <= 4
+    rows = torch.from_numpy(ref["rows"]).cuda()
+    cells = torch.from_numpy(ref["cells"]).cuda()
+    errB = rel(host(Bt.grad[rows]), ref["dB_rows"])
+    dk = ref["dkappa_cells"]
+    scale = np.maximum(np.abs(dk), 1e-3 * float(ref["dkappa_absmax"]))
+    errk = float(np.max(np.abs(host(kt.grad[cells]) - dk) / scale))
     log(f"dL/dB largest column error {errB:.2e}; dL/dkappa largest scaled error {errk:.2e}")
     assert errB <= 1e-9
     assert errk <= 1e-8

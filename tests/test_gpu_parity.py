@@ -95,14 +95,20 @@ def test_fixed_iterations_k_p_grid(k, variant, p):
     assert rel(host(Xg), Xo) <= FIXED_TOL
 
 
-@pytest.mark.parametrize("gw", ["1", "2"])
+@pytest.mark.parametrize("gw", ["1", "2", "vec", "mfma"])
 @pytest.mark.parametrize("k,variant,p", [(32, "hybrid", 16), (64, "hybrid", 4), (128, "hybrid", 16),
                                          (128, "global", 1), (32, "parallel", 1)])
 def test_update_groups_per_wave(monkeypatch, k, variant, p, gw):
     # the matrix-core update passes with one or two column groups per wave
-    # (two: both groups' rows move as whole lines); FP64 iterates against the
-    # oracle, ragged row count
-    monkeypatch.setenv("BCG_UPDATE_GW", gw)
+    # (two: both groups' rows move as whole lines), or the k-specialised vector
+    # update passes beside the matrix-core sparse product; FP64 iterates
+    # against the oracle, ragged row count
+    if gw == "vec":
+        monkeypatch.setenv("BCG_UPDATE_VEC64", "3")
+    elif gw == "mfma":
+        monkeypatch.setenv("BCG_UPDATE_VEC64", "0")
+    else:
+        monkeypatch.setenv("BCG_UPDATE_GW", gw)
     log(f"groups per wave {gw}: k={k} {variant} p={p}")
     N = 29
     A = stencil_csr(2, N, cell_coefficients(2, N, 0.7))
@@ -363,6 +369,30 @@ def _tiled_order(N, T):
     return np.concatenate(parts).astype(np.int32)
 
 
+def _brick_order(N, tile, brick):
+    """Definition of the brick schedule: key (tile column (ty, tx), tile z,
+    brick z, y, x inside the tile, cell z, y, x inside the brick)."""
+    z, y, x = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    x, y, z = x.ravel(), y.ravel(), z.ravel()
+    tx, ty, tz = tile
+    bx, by, bz = brick
+    tile_id = ((y // ty) * (N // tx) + x // tx) * (N // tz) + z // tz
+    lx, ly, lz = x % tx, y % ty, z % tz
+    brick_id = ((lz // bz) * (ty // by) + ly // by) * (tx // bx) + lx // bx
+    cell = ((lz % bz) * by + ly % by) * bx + lx % bx
+    key = (tile_id * (tx * ty * tz) + brick_id * (bx * by * bz) + cell).astype(np.int64)
+    return np.argsort(key, kind="stable").astype(np.int32)
+
+
+@pytest.mark.parametrize("N,tile,brick", [(8, (4, 4, 2), (2, 2, 2)), (12, (6, 4, 3), (3, 2, 1)),
+                                          (32, (16, 32, 2), (4, 2, 2)), (16, (16, 16, 16), (16, 1, 1))])
+def test_brick_schedule_matches_definition(N, tile, brick):
+    P = _lib()
+    got = host(P.stencil_brick_schedule(N, tile, brick))
+    assert np.array_equal(got, _brick_order(N, tile, brick))
+    assert np.array_equal(np.sort(got), np.arange(N ** 3))
+
+
 @pytest.mark.parametrize("N,T", [(5, 2), (13, 4), (128, 32)])
 def test_stencil_schedule_matches_definition(N, T):
     P = _lib()
@@ -381,7 +411,8 @@ def test_row_schedule_random_and_tiled(k, variant, p):
     A = stencil_csr(3, N, cell_coefficients(3, N, 0.6))
     B = rhs(A.shape[0], k, "normal", seed=21)
     Xo, _ = oracle_solve(A, B, variant, p, tol=0.0, maxit=7)
-    for order in (np.random.default_rng(5).permutation(A.shape[0]).astype(np.int32), _tiled_order(N, 4)):
+    bricks = _brick_order(N, (N, 1, 1), (1, 1, 1)) if N % 2 else _brick_order(N, (4, 2, 2), (2, 2, 1))
+    for order in (np.random.default_rng(5).permutation(A.shape[0]).astype(np.int32), _tiled_order(N, 4), bricks):
         s = _solver(A, k, variant, p)
         s.set_row_schedule(dev(order))
         Xg, ig = s.solve(dev(B), tol=0.0, maxit=7)

@@ -59,7 +59,8 @@ FP32_CASES = [(16, "block", 0), (16, "hybrid", 4), (16, "parallel", 1), (32, "bl
               (128, "hybrid", 16), (128, "global", 1)]
 
 
-@pytest.mark.parametrize("path", ["default", "no_mfma", "wide_offsets", "one_group_per_wave"])
+@pytest.mark.parametrize("path", ["default", "no_mfma", "wide_offsets", "one_group_per_wave", "vector_updates",
+                                  "matrix_core_updates"])
 @pytest.mark.parametrize("k,variant,p", FP32_CASES)
 def test_fp32_inner_iterations_match_oracle(monkeypatch, k, variant, p, path):
     """One refinement step with 6 FP32 inner iterations against the oracle's.
@@ -74,6 +75,10 @@ def test_fp32_inner_iterations_match_oracle(monkeypatch, k, variant, p, path):
         monkeypatch.setenv("BCG_WIDE_OFFSETS", "1")
     if path == "one_group_per_wave":  # update passes without paired 16-column groups
         monkeypatch.setenv("BCG_UPDATE_GW", "1")
+    if path == "vector_updates":  # k-specialised vector update passes, matrix-core sparse product
+        monkeypatch.setenv("BCG_UPDATE_VEC32", "3")
+    if path == "matrix_core_updates":  # matrix-core update passes wherever the plan has them
+        monkeypatch.setenv("BCG_UPDATE_VEC32", "0")
     from oracle import refine
     log(f"fp32 inner k={k} {variant} p={p} {path}")
     P = _P()

@@ -63,6 +63,17 @@ def test_argument_validation_without_device(lib):
     lib.bcg_destroy(None)
 
 
+def test_brick_schedule_rejects_sizes_without_device(lib):
+    from paper_1912_11930_amd import _capi
+    three = ctypes.c_int * 3
+    f = lib.bcg_stencil_brick_schedule
+    assert f(32, three(16, 32, 2), three(4, 2, 2), None, None) == _capi.BCG_EINVAL      # order NULL
+    assert f(32, three(12, 32, 2), three(4, 2, 2), 1, None) == _capi.BCG_EINVAL         # tile does not divide N
+    assert f(32, three(16, 32, 2), three(3, 2, 2), 1, None) == _capi.BCG_EINVAL         # brick does not divide tile
+    assert f(0, three(1, 1, 1), three(1, 1, 1), 1, None) == _capi.BCG_EINVAL
+    assert f(1300, three(1, 1, 1), three(1, 1, 1), 1, None) == _capi.BCG_EINVAL         # N^3 beyond int32
+
+
 def test_noalloc_argument_validation_without_device(lib):
     # every rejection below happens on the host, before the fixed array is touched
     from paper_1912_11930_amd import _capi
