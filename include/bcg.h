@@ -143,7 +143,8 @@ int bcg_set_stream(bcg_handle *h, void *hip_stream);
  *   inner_tol    replacement threshold delta: the FP64 correction and
  *                residual replacement happen whenever the FP32 recursive
  *                residual has fallen to delta times its value at the last
- *                correction, or to tol (0 < delta < 1; 0 selects 1e-2).
+ *                correction, or to tol (0 <= delta < 1; 0 selects 1e-2 for
+ *                groups of p <= 16 and 1e-1 for wider ones).
  *   inner_maxit  cap on FP32 iterations between two corrections.
  *   max_outer    cap on corrections.
  *   After a correction X += s D, R = B - A X (FP64), s' = max_j ||R_j||,

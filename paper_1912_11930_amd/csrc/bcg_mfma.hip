@@ -60,6 +60,32 @@ __device__ __forceinline__ void static_for(F&& f) {
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+// FP32 16x16x4 product (FP32 products and accumulation). Its result lane l,
+// element r holds D[4 (l >> 4) + r][l & 15] (measured on gfx950), where the
+// FP64 one holds D[4r + (l >> 4)][l & 15]; the update passes feed it the A
+// rows in the order tau, which gives the FP64 result layout (see load_a).
+__device__ __forceinline__ f4v mfma32(float a, float b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Matrix-core products of the updates per precision: FP64 block vectors on
+// the FP64 product, FP32 ones on the FP32 product (the update is an FP32
+// operation on FP32 data with FP32-rounded coefficients; only the block
+// products of the Grams accumulate in FP64).
+template <typename T>
+struct MT;
+template <>
+struct MT<double> {
+  using acc = d4;
+  __device__ static acc zero() { return d4{0.0, 0.0, 0.0, 0.0}; }
+  __device__ static acc fma(double a, double b, acc c) { return mfma(a, b, c); }
+};
+template <>
+struct MT<float> {
+  using acc = f4v;
+  __device__ static acc zero() { return f4v{0.0f, 0.0f, 0.0f, 0.0f}; }
+  __device__ static acc fma(float a, float b, acc c) { return mfma32(a, b, c); }
+};
 
 __device__ __forceinline__ bool mstopped(const DevState* st) {
   return st != nullptr && *reinterpret_cast<const volatile int*>(&st->done) != 0;
@@ -235,6 +261,13 @@ struct Coeff {
       return lds[c * PW * Gm::CST + coeff_row<T>(ab, kk, lane) * Gm::CST + jb * 16 + ord16<T>(lane & 15)];
     }
   }
+  // the operand in the block vectors' precision (FP32: the FP32-rounded value)
+  __device__ __forceinline__ T bt(int c, int ab, int jb, int kk, int lane) const {
+    if constexpr (Gm::BREG)
+      return r[c][(ab * NB + jb) * 4 + kk];
+    else
+      return static_cast<T>(b(c, ab, jb, kk, lane));
+  }
 };
 
 // Value of lane l^8 (DPP row_ror:8 within each row of 16 lanes).
@@ -262,10 +295,13 @@ __device__ __forceinline__ double xch(double x) {
 // which one DPP swap between lanes l and l ^ 8 delivers. (Loading each
 // lane's own row twice covers only half of each line per instruction; with
 // non-temporal loads every half-line then costs its own DRAM access.)
+//
+// FP32 (the operand of the FP32 product): lane l holds tile row tau(l & 15),
+// so that the product's result tile comes out in the FP64 layout.
 template <typename T, int K, int PW, bool NT>
-__device__ __forceinline__ void load_a(double (&a)[4], const T* __restrict__ X, int64_t row0, int64_t n, int G, int ab,
+__device__ __forceinline__ void load_a(T (&a)[4], const T* __restrict__ X, int64_t row0, int64_t n, int G, int ab,
                                        int lane) {
-  const int64_t r = row0 + (lane & 15);
+  const int64_t r = row0 + (sizeof(T) == 8 ? (lane & 15) : tau16(lane & 15));
   const bool ok = r < n;
   if constexpr (sizeof(T) == 8) {
     const int s = lane >> 4, b3 = (lane >> 3) & 1;
@@ -293,10 +329,10 @@ __device__ __forceinline__ void load_a(double (&a)[4], const T* __restrict__ X, 
       v = __builtin_nontemporal_load(src);
     else
       v = *src;
-    a[0] = ok ? static_cast<double>(v.x) : 0.0;
-    a[1] = ok ? static_cast<double>(v.y) : 0.0;
-    a[2] = ok ? static_cast<double>(v.z) : 0.0;
-    a[3] = ok ? static_cast<double>(v.w) : 0.0;
+    a[0] = ok ? v.x : 0.0f;
+    a[1] = ok ? v.y : 0.0f;
+    a[2] = ok ? v.z : 0.0f;
+    a[3] = ok ? v.w : 0.0f;
   }
 }
 
@@ -326,19 +362,28 @@ __device__ __forceinline__ void pair_st(float* Mt, int off, f4v v) {
     *dst = v;
 }
 
-// A operands: lane l holds row l & 15, columns 4s .. 4s + 3 (s = l >> 4) of
-// each group; rows past lim are zeroed.
+// A operands of the FP32 product: lane l holds tile row tau(l & 15) =
+// 4 (l & 3) + ((l >> 2) & 3) (the order under which the product's result tile
+// has the FP64 layout), columns 4s .. 4s + 3 (s = l >> 4) of each group; rows
+// past lim are zeroed. A lane's row lies in half h = bit 1 of l, so here the
+// lane whose bit 1 differs from the instruction's index moves the
+// second group's quad of the row of lane l ^ 2, and a DPP quad permutation
+// delivers it.
+__device__ __forceinline__ float qswap(float x) {  // value of lane l ^ 2
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));
+}
 template <bool NT>
 __device__ __forceinline__ void pair_load_a(float (&a0)[4], float (&a1)[4], const float* Mt, int lim, int K, int c0,
                                             int lane) {
-  const int b3 = (lane >> 3) & 1;
+  const int b1 = (lane >> 1) & 1;
+  const int row = tau16(lane & 15), prow = tau16((lane ^ 2) & 15);
   f4v u[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h)
-    u[h] = pair_ld<NT>(Mt, min((lane & 7) + 8 * h, lim) * K + c0 + (b3 == h ? 0 : 16) + 4 * (lane >> 4));
-  const f4v own = b3 ? u[1] : u[0], w = b3 ? u[0] : u[1];
-  const bool ok = (lane & 15) <= lim;
-  const float o[4] = {xch(w.x), xch(w.y), xch(w.z), xch(w.w)};
+    u[h] = pair_ld<NT>(Mt, min(b1 == h ? row : prow, lim) * K + c0 + (b1 == h ? 0 : 16) + 4 * (lane >> 4));
+  const f4v own = b1 ? u[1] : u[0], w = b1 ? u[0] : u[1];
+  const bool ok = row <= lim;
+  const float o[4] = {qswap(w.x), qswap(w.y), qswap(w.z), qswap(w.w)};
   const float m[4] = {own.x, own.y, own.z, own.w};
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
@@ -536,6 +581,10 @@ __device__ __forceinline__ void to_rows(const d4& D, float (&v)[4], int lane) {
                       static_cast<float>(D[3])};
   transpose4(d, v, (lane >> 2) & 3);
 }
+__device__ __forceinline__ void to_rows(const f4v& D, float (&v)[4], int lane) {
+  const float d[4] = {D[0], D[1], D[2], D[3]};
+  transpose4(d, v, (lane >> 2) & 3);
+}
 __device__ __forceinline__ void from_rows(const float (&v)[4], double (&x)[4], int lane) {
   float w[4];
   transpose4(v, w, (lane >> 2) & 3);
@@ -659,7 +708,7 @@ __global__ __launch_bounds__(kBlock) void k_update_r_mfma(Plan pl, T* __restrict
   MAcc<NB> acc[GW];
 #pragma unroll
   for (int g = 0; g < GW; ++g) acc[g].zero();
-  double qa[NB][4];
+  T qa[NB][4];
   T ra[NB][4];
   auto load_rows = [&](int64_t t, int G, int jb, T (&r)[4]) {
     const int cbase = G * PW + L::col(lane);
@@ -669,7 +718,7 @@ __global__ __launch_bounds__(kBlock) void k_update_r_mfma(Plan pl, T* __restrict
       L::template load_p<NT>(R + row * K + cbase + jb * 16, r + m * L::NC);
     }
   };
-  auto load_unit = [&](int64_t t, int G, double (&q)[NB][4], T (&r)[NB][4]) {
+  auto load_unit = [&](int64_t t, int G, T (&q)[NB][4], T (&r)[NB][4]) {
 #pragma unroll
     for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW, NT>(q[ab], Q, t * 16, n, G, ab, lane);
 #pragma unroll
@@ -695,9 +744,9 @@ __global__ __launch_bounds__(kBlock) void k_update_r_mfma(Plan pl, T* __restrict
       double rn[2][1][4];
 #pragma unroll
       for (int g = 0; g < 2; ++g) {
-        d4 D = {0.0, 0.0, 0.0, 0.0};
+        f4v D = MT<float>::zero();
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) D = mfma(static_cast<double>(q2[g][kk]), cf[g].b(0, 0, 0, kk, lane), D);
+        for (int kk = 0; kk < 4; ++kk) D = mfma32(q2[g][kk], cf[g].bt(0, 0, 0, kk, lane), D);
         float dq[4];
         to_rows(D, dq, lane);
 #pragma unroll
@@ -723,7 +772,7 @@ __global__ __launch_bounds__(kBlock) void k_update_r_mfma(Plan pl, T* __restrict
       constexpr int g = decltype(gc)::value;
       const int G = G0 + g;
       const int cbase = G * PW + L::col(lane);
-      double qn[NB][4];
+      T qn[NB][4];
       T rnx[NB][4];
       if constexpr (PIPE) {
         if constexpr (g + 1 < GW)
@@ -737,11 +786,11 @@ __global__ __launch_bounds__(kBlock) void k_update_r_mfma(Plan pl, T* __restrict
       double rn[NB][4];
 #pragma unroll
       for (int jb = 0; jb < NB; ++jb) {
-        d4 D = {0.0, 0.0, 0.0, 0.0};
+        auto D = MT<T>::zero();
 #pragma unroll
         for (int ab = 0; ab < NB; ++ab)
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) D = mfma(qa[ab][kk], cf[g].b(0, ab, jb, kk, lane), D);
+          for (int kk = 0; kk < 4; ++kk) D = MT<T>::fma(qa[ab][kk], cf[g].bt(0, ab, jb, kk, lane), D);
         if constexpr (!PIPE) load_rows(t, G, jb, ra[jb]);
         T dq[4], rv[4];
         to_rows(D, dq, lane);
@@ -797,7 +846,7 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restric
   MAcc<NB> acc[GW];
 #pragma unroll
   for (int g = 0; g < GW; ++g) acc[g].zero();
-  double pa[NB][4];
+  T pa[NB][4];
   T xa[NB][4], ra[NB][4];
   auto load_rows = [&](int64_t t, int G, int jb, T (&x)[4], T (&r)[4]) {
     const int cbase = G * PW + L::col(lane);
@@ -808,7 +857,7 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restric
       if (!last) L::template load_p<NT>(R + off, r + m * L::NC);
     }
   };
-  auto load_unit = [&](int64_t t, int G, double (&pq)[NB][4], T (&x)[NB][4], T (&r)[NB][4]) {
+  auto load_unit = [&](int64_t t, int G, T (&pq)[NB][4], T (&x)[NB][4], T (&r)[NB][4]) {
 #pragma unroll
     for (int ab = 0; ab < NB; ++ab) load_a<T, K, PW, NT>(pq[ab], Pm, t * 16, n, G, ab, lane);
 #pragma unroll
@@ -835,14 +884,14 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restric
       double pn[2][1][4], rd[2][1][4];
 #pragma unroll
       for (int g = 0; g < 2; ++g) {
-        d4 Dx = {0.0, 0.0, 0.0, 0.0}, Dp = {0.0, 0.0, 0.0, 0.0};
+        f4v Dx = MT<float>::zero(), Dp = MT<float>::zero();
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) Dx = mfma(static_cast<double>(p2[g][kk]), cf[g].b(0, 0, 0, kk, lane), Dx);
+        for (int kk = 0; kk < 4; ++kk) Dx = mfma32(p2[g][kk], cf[g].bt(0, 0, 0, kk, lane), Dx);
         float dx[4], dp[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         to_rows(Dx, dx, lane);
         if (!last) {
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) Dp = mfma(static_cast<double>(p2[g][kk]), cf[g].b(1, 0, 0, kk, lane), Dp);
+          for (int kk = 0; kk < 4; ++kk) Dp = mfma32(p2[g][kk], cf[g].bt(1, 0, 0, kk, lane), Dp);
           to_rows(Dp, dp, lane);
         }
 #pragma unroll
@@ -880,7 +929,7 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restric
       constexpr int g = decltype(gc)::value;
       const int G = G0 + g;
       const int cbase = G * PW + L::col(lane);
-      double pnx[NB][4];
+      T pnx[NB][4];
       T xnx[NB][4], rnx[NB][4];
       if constexpr (PIPE) {
         if constexpr (g + 1 < GW)
@@ -894,11 +943,11 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restric
       double pn[NB][4], rd[NB][4];
 #pragma unroll
       for (int jb = 0; jb < NB; ++jb) {
-        d4 Dx = {0.0, 0.0, 0.0, 0.0}, Dp = {0.0, 0.0, 0.0, 0.0};
+        auto Dx = MT<T>::zero(), Dp = MT<T>::zero();
 #pragma unroll
         for (int ab = 0; ab < NB; ++ab)
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) Dx = mfma(pa[ab][kk], cf[g].b(0, ab, jb, kk, lane), Dx);
+          for (int kk = 0; kk < 4; ++kk) Dx = MT<T>::fma(pa[ab][kk], cf[g].bt(0, ab, jb, kk, lane), Dx);
         if constexpr (!PIPE) load_rows(t, G, jb, xa[jb], ra[jb]);
         T dx[4], dp[4], pv[4], rv[4];
         to_rows(Dx, dx, lane);
@@ -906,7 +955,7 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_mfma(Plan pl, T* __restric
 #pragma unroll
           for (int ab = 0; ab < NB; ++ab)
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) Dp = mfma(pa[ab][kk], cf[g].b(1, ab, jb, kk, lane), Dp);
+            for (int kk = 0; kk < 4; ++kk) Dp = MT<T>::fma(pa[ab][kk], cf[g].bt(1, ab, jb, kk, lane), Dp);
           to_rows(Dp, dp, lane);
         }
 #pragma unroll
