@@ -286,7 +286,7 @@ def main() -> int:
                     help="sparse product on SELL-16-SIGMA storage (SIGMA 1 or a multiple of 16; 0: CSR)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (counter calibration)")
-    ap.add_argument("--study", default=None, choices=["repeat128", "gradient", "sell"],
+    ap.add_argument("--study", default=None, choices=["repeat128", "gradient", "sell", "paths"],
                     help="repeat128: time to solve 128 right-hand sides in 128/k solves, k = 16..128, p = 16; "
                          "gradient: forward + adjoint backward of the 512^2 diffusion workload")
     ap.add_argument("--study-precisions", default="fp32_refine,fp64")
@@ -302,7 +302,7 @@ def main() -> int:
         if args.gpus != 1:
             log("bench.py: only --gpus 1 is supported")
             return 2
-        studies = {"repeat128": repeat_study, "gradient": gradient_study, "sell": sell_study}
+        studies = {"repeat128": repeat_study, "gradient": gradient_study, "sell": sell_study, "paths": paths_study}
         return studies[args.study](args)
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1",
@@ -715,6 +715,80 @@ def sell_study(args) -> int:
                 print(json.dumps(line), flush=True)
             del solver
             torch.cuda.empty_cache()
+    return 0
+
+
+def paths_study(args) -> int:
+    """Matrix-core against vector kernels for the row passes, by subalgebra
+    width (parallel, hybrid 4, 8 and 16), on the 128^3 Poisson system with
+    k = 16 and the 256^3 one with k = 128, both in the brick row order.
+    Paths: the library's choice; the matrix cores for every row pass
+    (BCG_UPDATE_VEC32 = BCG_UPDATE_VEC64 = 0, where the choice differs); the
+    k-specialised vector kernels (BCG_NO_MFMA). Each line: per-class average
+    launch times and the summed kernel time per iteration of a fixed number of
+    iterations (`--steps`, at least 10) after one untimed solve, FP64 and the
+    FP32 inner iteration (one outer step of exactly that many iterations)."""
+    import torch
+
+    import paper_1912_11930_amd as P
+    from workload import rhs
+
+    dev = torch.device("cuda:0")
+    m = max(args.steps, 10)
+    envs = ("BCG_NO_MFMA", "BCG_UPDATE_VEC32", "BCG_UPDATE_VEC64")
+    for N, k in ((128, 16), (256, 128)):
+        n = N ** 3
+        rp, ci, va = P.stencil(3, N, None, device=dev)
+        nnz = ci.numel()
+        order = P.stencil_brick_schedule(N, (16, 32, 2), (4, 2, 2), device=dev)
+        B = torch.from_numpy(rhs(n, k, "uniform")).to(dev)
+        X = torch.zeros_like(B)
+        for (variant, p), precision in itertools.product((("parallel", 1), ("hybrid", 4), ("hybrid", 8),
+                                                          ("hybrid", 16)), ("fp32_refine", "fp64")):
+            paths = [("default", {}), ("vector", {"BCG_NO_MFMA": "1"})]
+            wide = precision == "fp64" or p <= 8
+            if k == 128 and wide:  # the library puts some row passes on vector kernels here
+                paths.insert(1, ("matrix-core", {"BCG_UPDATE_VEC32": "0", "BCG_UPDATE_VEC64": "0"}))
+            for path, env in paths:
+                for e in envs:
+                    os.environ.pop(e, None)
+                os.environ.update(env)
+                solver = P.BCG(rp, ci, va, k=k, subalgebra=variant, p=p)
+                solver.set_row_schedule(order)
+                if precision == "fp64":
+                    solver.set_precision("fp64")
+                    tol = 0.0
+                else:
+                    solver.set_precision("fp32_refine", 0.0, m, 1)
+                    tol = 1e-8
+                X.zero_()
+                solver.solve(B, X, tol=tol, maxit=m)
+                solver.set_profiling(True)
+                X.zero_()
+                _, info = solver.solve(B, X, tol=tol, maxit=m)
+                times = solver.kernel_times()
+                solver.set_profiling(False)
+                solver.close()
+                del solver
+                its = max(info["iterations"], 1)
+                line = {"study": "paths", "system": f"poisson3d_{N}", "n": n, "k": k, "variant": variant, "p": p,
+                        "precision": "fp64" if precision == "fp64" else "fp32 inner", "path": path,
+                        "iterations": info["iterations"]}
+                for c in ("spmm", "update_r", "update_xp", "reduce", "small"):
+                    launches, total_ms = times[c]
+                    if launches:
+                        us = 1e3 * total_ms / launches
+                        line[f"{c}_us"] = round(us, 1)
+                        if c in ("spmm", "update_r", "update_xp"):
+                            line[f"{c}_GBps"] = round(
+                                algorithmic_bytes(c, n, nnz, k, precision) / (us * 1e-6) / 1e9, 1)
+                row_ms = sum(times[c][1] for c in ("spmm", "update_r", "update_xp", "reduce", "small"))
+                line["ms_per_iteration"] = round(row_ms / its, 3)
+                print(json.dumps(line), flush=True)
+            for e in envs:
+                os.environ.pop(e, None)
+        del B, X
+        torch.cuda.empty_cache()
     return 0
 
 

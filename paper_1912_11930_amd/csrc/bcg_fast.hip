@@ -282,15 +282,27 @@ struct CoopIdx {
 // gathers of step s, then the first index chunk of step s+1 (its CSR range
 // was loaded one step earlier), then the CSR range of step s+2, and only then
 // consumes the gathers.
-template <typename T, int K, int P>
+// Residual modes (FP64; Algorithm 1's initial residual, and the true residual
+// of a refinement step): Pm is X, Bm is B and Q receives R = B - A X, with
+// the column norms; kResidP also stores P = R (Pout) and, when the plan fuses
+// products, the partial <<R, R>>.
+enum FastMode { kProduct = 0, kResidual = 1, kResidP = 2 };
+template <typename T, int K, int P, int MODE = kProduct>
 __global__ __launch_bounds__(kBlock) void k_spmm_fast(Plan pl, const int32_t* __restrict__ rowptr,
                                                       const int32_t* __restrict__ colind, const T* __restrict__ vals,
                                                       const T* __restrict__ Pm, T* __restrict__ Q,
-                                                      double* __restrict__ part, const DevState* st) {
+                                                      double* __restrict__ part, const DevState* st,
+                                                      const T* __restrict__ Bm = nullptr,
+                                                      T* __restrict__ Pout = nullptr) {
   if (halted(st)) return;
   using Gm = Geo<K, P>;
   using T2 = typename V2<T>::type;
-  __shared__ T slab[4][Gm::NEED_LDS ? Gm::SLAB : 1];
+  constexpr bool RES = MODE != kProduct;
+  static_assert(!RES || sizeof(T) == 8, "the residual is formed in FP64");
+  // the row slab in LDS serves the Gram of a group wider than one lane
+  constexpr bool SLAB = Gm::NEED_LDS && MODE != kResidual;
+  const bool gram = MODE == kProduct || (MODE == kResidP && pl.fused);
+  __shared__ T slab[4][SLAB ? Gm::SLAB : 1];
   __shared__ double H[K * P + K];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int rr = lane / Gm::G, cg = lane - rr * Gm::G, c0 = 2 * cg;
@@ -337,11 +349,11 @@ __global__ __launch_bounds__(kBlock) void k_spmm_fast(Plan pl, const int32_t* __
   for (; s < sr.end; s += tw) {
     const bool ok = s * Gm::RW + rr < n;
     const int64_t i = cur_row;
-    // 1. gathers of the current step and its own row of P
+    // 1. gathers of the current step and its own row of P (of B)
     T2 xv[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) xv[u] = *reinterpret_cast<const T2*>(Pm + (int64_t)cur.cols[u] * K + c0);
-    const T2 pv = *reinterpret_cast<const T2*>(Pm + i * K + c0);
+    const T2 pv = *reinterpret_cast<const T2*>((RES ? Bm : Pm) + i * K + c0);
     // 2. index chunk of the next step (CSR range already loaded)
     RowIdx<T> nxt;
     nxt.j0 = nj0;
@@ -384,29 +396,47 @@ __global__ __launch_bounds__(kBlock) void k_spmm_fast(Plan pl, const int32_t* __
       }
     }
     T po[2] = {T(0), T(0)};
-    if (ok) {
+    if constexpr (RES) {
+      // R = B - A X; rows past n add nothing
+      if (ok) {
+        q[0] = pv.x - q[0];
+        q[1] = pv.y - q[1];
+        *reinterpret_cast<T2*>(Q + i * K + c0) = T2{q[0], q[1]};
+        if constexpr (MODE == kResidP) *reinterpret_cast<T2*>(Pout + i * K + c0) = T2{q[0], q[1]};
+      } else {
+        q[0] = q[1] = T(0);
+      }
+      po[0] = q[0];
+      po[1] = q[1];
+#pragma unroll
+      for (int v = 0; v < 2; ++v) acc.nrm[v] = fma(q[v], q[v], acc.nrm[v]);
+    } else if (ok) {
       *reinterpret_cast<T2*>(Q + i * K + c0) = T2{q[0], q[1]};
       po[0] = pv.x;
       po[1] = pv.y;
     } else {
       q[0] = q[1] = T(0);
     }
-    const T* xs = nullptr;
-    if constexpr (Gm::NEED_LDS) {
-      T* sl = slab[wave];
-      *reinterpret_cast<T2*>(sl + rr * K + c0) = T2{po[0], po[1]};
-      wave_sync();
-      xs = sl + rr * K + gcol;
+    if constexpr (MODE != kResidual) {
+      if (gram) {
+        const T* xs = nullptr;
+        if constexpr (SLAB) {
+          T* sl = slab[wave];
+          *reinterpret_cast<T2*>(sl + rr * K + c0) = T2{po[0], po[1]};
+          wave_sync();
+          xs = sl + rr * K + gcol;
+        }
+        acc_row<T, P>(acc, xs, po, q);  // alpha = <<P, Q>> (a over P, b over Q), or <<R, R>>
+        if constexpr (SLAB) wave_sync();
+      }
     }
-    acc_row<T, P>(acc, xs, po, q);  // alpha = <<P, Q>>: a over P, b over Q
-    if constexpr (Gm::NEED_LDS) wave_sync();
     if constexpr (Gm::G <= 32) cnx.spread(nxt);
     cur = nxt;
     cur_row = row1;
     row1 = row2;
     row2 = row3;
   }
-  finish_partial<K, P, false>(acc, H, part + (int64_t)blockIdx.x * pl.W, pl);
+  finish_partial<K, P, RES>(acc, H, part + (int64_t)blockIdx.x * pl.W, pl);
 }
 
 // ------------------------------------------------------------ R update
@@ -479,6 +509,67 @@ __global__ __launch_bounds__(kBlock) void k_update_r_fast(Plan pl, T* __restrict
     acc_row<T, P>(acc, rs, rn, rn);  // <<R, R>>
 #pragma unroll
     for (int v = 0; v < 2; ++v) acc.nrm[v] = fma((double)rn[v], (double)rn[v], acc.nrm[v]);
+    if constexpr (Gm::NEED_LDS) wave_sync();
+  }
+  finish_partial<K, P, true>(acc, H, part + (int64_t)blockIdx.x * pl.W, pl);
+}
+
+// ------------------------------------------------ FP32 start of a refinement
+// R32 = R64 / s with s = max_j sqrt(norms[j]) (stored to *scale), D32 = 0 and
+// P32 = R32 (pfac = 0) or P32 *= pfac rounded to FP32 (residual replacement),
+// with the partial <<R32, R32>> (FP64 accumulation) and the column norms.
+template <int K, int P>
+__global__ __launch_bounds__(kBlock) void k_cast_init_fast(Plan pl, const double* __restrict__ R64,
+                                                           const double* __restrict__ norms, float* __restrict__ R32,
+                                                           float* __restrict__ P32, float* __restrict__ D32,
+                                                           double* __restrict__ scale, double* __restrict__ part,
+                                                           double pfac) {
+  using Gm = Geo<K, P>;
+  __shared__ float slab[4][Gm::NEED_LDS ? Gm::SLAB : 1];
+  __shared__ double H[K * P + K];
+  __shared__ double s_sh;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int rr = lane / Gm::G, cg = lane - rr * Gm::G, c0 = 2 * cg;
+  const int gcol = (c0 / P) * P;
+  if (tid == 0) {
+    double m = 0.0;
+    for (int j = 0; j < K; ++j) m = fmax(m, sqrt(norms[j]));
+    s_sh = m;
+    if (blockIdx.x == 0) *scale = m;
+  }
+  __syncthreads();
+  const double sc = s_sh;
+  const float pf = static_cast<float>(pfac);
+  LaneAcc<P> acc;
+  acc.zero();
+  const int64_t nsteps = (pl.n + Gm::RW - 1) / Gm::RW;
+  const StepRange sr = wave_steps(nsteps);
+  const int64_t n = pl.n;
+  for (int64_t s = sr.first; s < sr.end; s += sr.stride) {
+    const int64_t i = s * Gm::RW + rr;
+    const bool ok = i < n;
+    const int64_t off = (ok ? i : n - 1) * K + c0;
+    const double2 r = *reinterpret_cast<const double2*>(R64 + off);
+    float2 pv{0.f, 0.f};
+    if (pfac != 0.0) pv = *reinterpret_cast<const float2*>(P32 + off);
+    float v[2] = {0.f, 0.f};
+    if (ok) {
+      v[0] = static_cast<float>(r.x / sc);
+      v[1] = static_cast<float>(r.y / sc);
+      *reinterpret_cast<float2*>(R32 + off) = float2{v[0], v[1]};
+      *reinterpret_cast<float2*>(P32 + off) = pfac == 0.0 ? float2{v[0], v[1]} : float2{pv.x * pf, pv.y * pf};
+      *reinterpret_cast<float2*>(D32 + off) = float2{0.f, 0.f};
+    }
+    const float* vs = nullptr;
+    if constexpr (Gm::NEED_LDS) {
+      float* sl = slab[wave];
+      *reinterpret_cast<float2*>(sl + rr * K + c0) = float2{v[0], v[1]};
+      wave_sync();
+      vs = sl + rr * K + gcol;
+    }
+    if (pl.fused) acc_row<float, P>(acc, vs, v, v);  // <<R32, R32>>
+#pragma unroll
+    for (int u = 0; u < 2; ++u) acc.nrm[u] = fma((double)v[u], (double)v[u], acc.nrm[u]);
     if constexpr (Gm::NEED_LDS) wave_sync();
   }
   finish_partial<K, P, true>(acc, H, part + (int64_t)blockIdx.x * pl.W, pl);
@@ -607,6 +698,28 @@ void launch_spmm_fast(const Plan& pl, const int32_t* rowptr, const int32_t* coli
   dispatch_fast(pl, [&](auto Kc, auto Pc) {
     hipLaunchKernelGGL((k_spmm_fast<T, decltype(Kc)::value, decltype(Pc)::value>), dim3(pl.nwg), dim3(kBlock), 0, s,
                        pl, rowptr, colind, vals, P, Q, part, st);
+  });
+}
+
+bool launch_residual_fast(const Plan& pl, const int32_t* rowptr, const int32_t* colind, const double* vals,
+                          const double* B, const double* X, double* R, double* P, double* part, int with_p,
+                          hipStream_t s) {
+  return dispatch_fast(pl, [&](auto Kc, auto Pc) {
+    constexpr int K = decltype(Kc)::value, PP = decltype(Pc)::value;
+    if (with_p)
+      hipLaunchKernelGGL((k_spmm_fast<double, K, PP, kResidP>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, rowptr, colind,
+                         vals, X, R, part, nullptr, B, P);
+    else
+      hipLaunchKernelGGL((k_spmm_fast<double, K, PP, kResidual>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, rowptr,
+                         colind, vals, X, R, part, nullptr, B, nullptr);
+  });
+}
+
+bool launch_cast_init_fast(const Plan& pl, const double* R64, const double* norms, float* R32, float* P32,
+                           float* D32, double* scale, double* part, hipStream_t s, double pfac) {
+  return dispatch_fast(pl, [&](auto Kc, auto Pc) {
+    hipLaunchKernelGGL((k_cast_init_fast<decltype(Kc)::value, decltype(Pc)::value>), dim3(pl.nwg), dim3(kBlock), 0,
+                       s, pl, R64, norms, R32, P32, D32, scale, part, pfac);
   });
 }
 

@@ -150,6 +150,15 @@ void launch_check_perm(const int32_t* order, int64_t n, int* seen, int* flag, hi
 void launch_check_csr(const int32_t* rowptr, const int32_t* colind, int64_t n, int64_t nnz, int* flag,
                       hipStream_t s);
 // k-specialised row kernels (16-byte aligned block vectors; see fast_supported)
+// R = B - A X with the column norms (with_p: also P = R and, when fused, the
+// partial <<R, R>>); false when the plan has no k-specialised kernels
+bool launch_residual_fast(const Plan& pl, const int32_t* rowptr, const int32_t* colind, const double* vals,
+                          const double* B, const double* X, double* R, double* P, double* part, int with_p,
+                          hipStream_t s);
+// FP32 start of a refinement step (see launch_cast_init); false when the plan
+// has no k-specialised kernels
+bool launch_cast_init_fast(const Plan& pl, const double* R64, const double* norms, float* R32, float* P32,
+                           float* D32, double* scale, double* part, hipStream_t s, double pfac);
 template <typename T>
 void launch_spmm_fast(const Plan& pl, const int32_t* rowptr, const int32_t* colind, const T* vals, const T* P,
                       T* Q, double* part, const DevState* st, hipStream_t s);

@@ -1591,6 +1591,13 @@ Plan make_plan(int64_t n, int64_t nnz, int k, int p, int global, int dec) {
 void launch_residual(const Plan& pl, const int32_t* rowptr, const int32_t* colind, const double* vals,
                      const double* B, const double* X, double* R, double* P, double* part, int with_p,
                      hipStream_t s) {
+  // the k-specialised gather kernel where the plan has one and every block
+  // vector is 16-byte aligned (it moves two columns per lane)
+  const uintptr_t al = reinterpret_cast<uintptr_t>(B) | reinterpret_cast<uintptr_t>(X) |
+                       reinterpret_cast<uintptr_t>(R) | reinterpret_cast<uintptr_t>(with_p ? P : R);
+  if (pl.fast && al % 16 == 0 && (!with_p || pl.fused) &&
+      launch_residual_fast(pl, rowptr, colind, vals, B, X, R, P, part, with_p, s))
+    return;
   dispatch_shape(pl, [&](auto RB, auto NAB) {
     hipLaunchKernelGGL((k_residual<decltype(RB)::value, decltype(NAB)::value>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, rowptr, colind, vals, B, X,
                        R, P, part, with_p);
@@ -1599,6 +1606,13 @@ void launch_residual(const Plan& pl, const int32_t* rowptr, const int32_t* colin
 
 void launch_cast_init(const Plan& pl, const double* R64, const double* norms, float* R32, float* P32, float* D32,
                       double* scale, double* part, hipStream_t s, double pfac) {
+  // the k-specialised kernel moves two columns per lane: every block 8-byte
+  // (FP32) or 16-byte (FP64) aligned
+  const uintptr_t al = reinterpret_cast<uintptr_t>(R32) | reinterpret_cast<uintptr_t>(P32) |
+                       reinterpret_cast<uintptr_t>(D32);
+  if (pl.fast && pl.fused && al % 8 == 0 && reinterpret_cast<uintptr_t>(R64) % 16 == 0 &&
+      launch_cast_init_fast(pl, R64, norms, R32, P32, D32, scale, part, s, pfac))
+    return;
   dispatch_shape(pl, [&](auto RB, auto NAB) {
     hipLaunchKernelGGL((k_cast_init<decltype(RB)::value, decltype(NAB)::value>), dim3(pl.nwg), dim3(kBlock), 0, s, pl, R64, norms, R32, P32, D32,
                        scale, part, pfac);

@@ -137,6 +137,7 @@ struct bcg_handle {
   std::vector<ProfRec> prof_recs;
   bcg_kernel_time prof[BCG_NUM_KERNEL_CLASSES]{};
   std::vector<double> ref_r0;  // host copy of the stop rule's reference norms
+  double known_true = -1.0;    // true relative residual of the returned X, when the solve measured it
   bcg_info info{};
   std::vector<double> host_ratios;
   // Jacobi preconditioning by symmetric scaling
@@ -645,12 +646,18 @@ int solve_reliable(bcg_handle* h, const double* B, double* X, double tol, int ma
     const double ratio = max_ratio(norms2, r0);
     for (int j = 0; j < h->k; ++j) h->host_ratios[j] = r0[j] == 0.0 ? 0.0 : std::sqrt(norms2[j]) / r0[j];
     if (!(ratio == ratio)) return fail(BCG_EBREAKDOWN, "non-finite residual during refinement");
-    if (ratio <= tol) return BCG_OK;
+    if (ratio <= tol) {
+      h->known_true = ratio;  // the residual of the X the solve returns
+      return BCG_OK;
+    }
     if (!(ratio <= 0.5 * last)) {
       fallback = true;  // no progress since the last correction
       break;
     }
-    if (corrections >= h->max_outer) return BCG_NOT_CONVERGED;
+    if (corrections >= h->max_outer) {
+      h->known_true = ratio;
+      return BCG_NOT_CONVERGED;
+    }
     last = ratio;
     // residual replacement in the new scale s'
     const double s_new = scale_of(norms2), f = s / s_new;
@@ -1118,6 +1125,7 @@ int bcg_solve(bcg_handle* h, const double* B, double* X, double tol, int maxit) 
   h->info = bcg_info{};
   h->info.k = h->k;
   h->ref_r0.clear();
+  h->known_true = -1.0;
   h->host_ratios.assign(h->k, 1.0);
   int its = 0;
   const double* Bsolve = B;
@@ -1155,8 +1163,12 @@ int bcg_solve(bcg_handle* h, const double* B, double* X, double tol, int maxit) 
   const hipError_t se = hipStreamSynchronize(h->stream);
   if (se != hipSuccess && rc >= 0) rc = fail(BCG_EHIP, "solve failed: %s", hipGetErrorString(se));
   if (h->prof_on) prof_collect(h, 0);  // set-up launches still pending
-  // true residual of the returned X relative to ||R0_j|| (Euclidean)
-  if (rc != BCG_EINVAL && rc != BCG_EHIP && rc != BCG_ENOMEM && (int)h->ref_r0.size() == h->k) {
+  // true residual of the returned X relative to ||R0_j|| (Euclidean); the
+  // residual-replacement solve has measured it already, unless it ran on the
+  // Jacobi-scaled system
+  if (!jac && h->known_true >= 0.0 && (rc == BCG_OK || rc == BCG_NOT_CONVERGED)) {
+    h->info.true_rel_res = h->known_true;
+  } else if (rc != BCG_EINVAL && rc != BCG_EHIP && rc != BCG_ENOMEM && (int)h->ref_r0.size() == h->k) {
     launch_residual(h->pl, h->rowptr, h->colind, h->vals, B, X, h->Q, nullptr, h->partN, 0, h->stream);
     launch_reduce(h->pl, h->partN, h->rnew, h->pl.W, nullptr, h->stream);
     std::vector<double> n2;

@@ -9,11 +9,12 @@ otherwise:
   the oracle's converged solves, stored by ``tests/golden/
   make_poisson3d_128_fixture.py`` (status, iteration count, final column
   ratios, the solution on 512 sampled rows), plus the true residual;
-* 192^3 diffusion, k = 64: one iteration against the oracle element by
-  element; FP32 + refinement to 1e-10 (hybrid 8, block 64) with the true
+* 192^3 diffusion, k = 64: one iteration against the oracle, column by
+  column; FP32 + refinement to 1e-10 (hybrid 8, block 64) with the true
   residual recomputed by the oracle's SciPy CSR matrix;
 * 512^2 diffusion, k = 32: forward + adjoint gradient against the oracle's
-  adjoint gradient (dL/dB and dL/dkappa, element by element);
+  adjoint gradient (dL/dB per column on sampled rows, dL/dkappa per sampled
+  cell);
 * 256^3 Poisson, k = 128: fixed FP64 iterations of hybrid 8 and 16 against
   the oracle on sampled column groups (exact: the groups of a hybrid solve
   are independent block CG solves, Section 2) and of global(1) on the full
@@ -44,6 +45,12 @@ def _P():
     return P
 
 
+def _order(w):
+    """The benchmark's row order of a 3D stencil: 4x2x2 bricks in 16x32x2
+    tiles swept through z."""
+    return _P().stencil_brick_schedule(w.N, (16, 32, 2), (4, 2, 2))
+
+
 @pytest.fixture(scope="module")
 def diffusion192():
     w = WORKLOADS["diffusion3d_192_k64"]
@@ -60,7 +67,7 @@ def test_diffusion3d_192_one_iteration(diffusion192, variant, p):
     Xo, io = oracle_solve(A, B, variant, p, tol=0.0, maxit=1)
     rp, ci, va = P.stencil(w.dim, w.N, torch.from_numpy(kappa).cuda())
     s = P.BCG(rp, ci, va, k=w.k, subalgebra=variant, p=p)
-    s.set_row_schedule(P.stencil_schedule(w.dim, w.N, 32))
+    s.set_row_schedule(_order(w))
     Xg, ig = s.solve(dev(B), tol=0.0, maxit=1)
     assert ig["iterations"] == io["iterations"] == 1
     assert ig["status"] == io["status"] == oracle.NOT_CONVERGED
@@ -85,20 +92,21 @@ def _poisson_residual_ratios(N, B, X):
 
 
 @pytest.mark.timeout(600)
-def test_poisson3d_128_k16_headline_form():
-    """The benchmark's headline form exactly: 128^3 Poisson, k = 16, block,
-    tiled row order, FP32+refinement to 1e-8. The true residual is recomputed
+@pytest.mark.parametrize("precision", ["fp32_refine", "fp32_reliable"])
+def test_poisson3d_128_k16_mixed_forms(precision):
+    """128^3 Poisson, k = 16, block, in the benchmark's row order, both mixed
+    forms (FP32 with FP64 refinement) to 1e-8. The true residual is recomputed
     with the plain PyTorch stencil; the solution must agree with the plain FP64
     solve to the accuracy both reach (each is within 1e-8 of the exact
     solution relative to the residual, so the solutions differ by about
     kappa * 1e-8)."""
     P = _P()
     w = WORKLOADS["poisson3d_128_k16"]
-    log("128^3 k=16 block, FP32+refinement to 1e-8 (headline form)")
+    log(f"128^3 k=16 block, {precision} to 1e-8")
     B = dev(rhs_for(w))
     s = P.BCG(*P.stencil(w.dim, w.N), k=w.k, subalgebra="block")
-    s.set_row_schedule(P.stencil_schedule(w.dim, w.N, 32))
-    s.set_precision("fp32_refine")
+    s.set_row_schedule(_order(w))
+    s.set_precision(precision)
     X, info = s.solve(B, tol=w.tol)
     log(f"status={info['status_name']} iterations={info['iterations']} outer={info['outer_iterations']} "
         f"true_rel_res={info['true_rel_res']:.2e}")
@@ -119,13 +127,13 @@ def poisson128():
     P = _P()
     w = WORKLOADS["poisson3d_128_k16"]
     ref = np.load(os.path.join(GOLDEN, "poisson3d_128_k16_fp64.npz"))
-    return w, ref, dev(rhs_for(w)), P.stencil(w.dim, w.N), P.stencil_schedule(w.dim, w.N, 32)
+    return w, ref, dev(rhs_for(w)), P.stencil(w.dim, w.N), _order(w)
 
 
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("variant,p", [("block", 16), ("global", 1), ("parallel", 1), ("hybrid", 4)])
 def test_poisson3d_128_converged_fp64(poisson128, variant, p):
-    """Converged FP64 solve to 1e-8 (tiled row order) against the oracle's:
+    """Converged FP64 solve to 1e-8 (the benchmark's row order) against the oracle's:
     same status and iteration count, column ratios of the stop rule to 1e-6
     relative, the solution on the 512 sampled rows to 1e-8 per column, and a
     true residual within the tolerance (recomputed independently)."""
@@ -154,7 +162,7 @@ def poisson256():
     P = _P()
     w = WORKLOADS["poisson3d_256_k128"]
     B = rhs_for(w)
-    return w, B, dev(B), P.stencil(w.dim, w.N), P.stencil_schedule(w.dim, w.N, 32)
+    return w, B, dev(B), P.stencil(w.dim, w.N), _order(w)
 
 
 @pytest.fixture(scope="module")
@@ -252,7 +260,7 @@ def test_diffusion3d_192_refinement_to_1e10(diffusion192, variant, p, precision)
     log(f"192^3 k=64 {variant} p={p}: {precision} to 1e-10")
     rp, ci, va = P.stencil(w.dim, w.N, torch.from_numpy(kappa).cuda())
     s = P.BCG(rp, ci, va, k=w.k, subalgebra=variant, p=p)
-    s.set_row_schedule(P.stencil_schedule(w.dim, w.N, 32))
+    s.set_row_schedule(_order(w))
     s.set_precision(precision)
     X, info = s.solve(dev(B), tol=w.tol, maxit=100000)
     log(f"status={info['status_name']} iterations={info['iterations']} outer={info['outer_iterations']} "

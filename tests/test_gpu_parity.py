@@ -1,8 +1,10 @@
-"""GPU (HIP) path vs the FP64 oracle, element by element, through the C ABI.
+"""GPU (HIP) path vs the FP64 oracle, column by column, through the C ABI.
 
 Tolerances (FP64): the two sides run the same recurrences with different
 summation orders, so they differ by rounding amplified along the iteration.
-Fixed-iteration iterates must agree to 1e-10 relative (Frobenius); converged
+Errors are the largest per-column relative error (``rel``), so that one bad
+column cannot hide in the norm of the others.
+Fixed-iteration iterates must agree to 1e-10 in every column; converged
 solves (tol 1e-8) must stop at the same iteration (a tie at the stop boundary
 may shift it by one) and agree to 1e-8 relative, the accuracy the method
 itself delivers. Integer and CSR work is compared bit for bit.
