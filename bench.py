@@ -113,7 +113,8 @@ def copy_calibration() -> int:
 
 
 def _pmc_means(db_path: str, counter: str) -> dict:
-    """Per-kernel mean counter value over dispatches that did work."""
+    """Per-kernel mean counter value over dispatches that did work, and their
+    number: {kernel: (mean, dispatches)}."""
     import sqlite3
     db = sqlite3.connect(db_path)
     cols = [r[1] for r in db.execute("pragma table_info(counters_collection)")]
@@ -127,7 +128,7 @@ def _pmc_means(db_path: str, counter: str) -> dict:
     for name, vals in per.items():
         top = max(vals)
         work = [v for v in vals if v > 0.01 * top]  # launches that returned at entry are dropped
-        out[name] = sum(work) / len(work) if work else 0.0
+        out[name] = (sum(work) / len(work) if work else 0.0, len(work))
     return out
 
 
@@ -148,7 +149,7 @@ def traffic_from(directory: str, workload: str, variant: str) -> int:
 
     def copy_kib(sub, counter):
         vals = _pmc_means(db(sub), counter)
-        return max(vals.values())
+        return max(v[0] for v in vals.values())
 
     f_fetch = (COPY_BYTES / 1024) / copy_kib("copy_fetch", "FETCH_SIZE")
     f_write = (COPY_BYTES / 1024) / copy_kib("copy_write", "WRITE_SIZE")
@@ -160,16 +161,20 @@ def traffic_from(directory: str, workload: str, variant: str) -> int:
         want32 = precision != "fp64"
         for cls, knames in KERNEL_NAMES.items():
             def pick(table):
-                return [v for nm, v in table.items()
+                # the class's kernel of the iteration: the one launched most
+                # (the residual modes of the k-specialised product run a few
+                # times per solve)
+                hits = [v for nm, v in table.items()
                         if any(kn in nm for kn in knames) and _is_fp32_kernel(nm) == want32]
+                return max(hits, key=lambda v: v[1])[0] if hits else None
             fk, wk = pick(fetch), pick(write)
-            if not fk or not wk:
+            if fk is None or wk is None:
                 continue
-            rd = fk[0] * 1024 * f_fetch
-            wr = wk[0] * 1024 * f_write
+            rd = fk * 1024 * f_fetch
+            wr = wk * 1024 * f_write
             rec[f"{cls}/{workload}/{variant}/{precision}"] = {
                 "bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr,
-                "fetch_kib": fk[0], "write_kib": wk[0], "fetch_scale": f_fetch, "write_scale": f_write,
+                "fetch_kib": fk, "write_kib": wk, "fetch_scale": f_fetch, "write_scale": f_write,
                 "kernel_hash": kernel_hash(),
             }
     with open(path, "w") as fh:
@@ -351,7 +356,7 @@ def main() -> int:
             sv.set_sell(True, args.sell)
         return sv
 
-    solver = make_solver(args.variant, args.p)
+    solver = make_solver(args.variant, p_eff)
     matrix_format = f"sell-16-{args.sell}" if args.sell else "csr"
     torch.cuda.synchronize()
     log(f"bench: set-up {time.perf_counter() - t_start:.1f} s")
