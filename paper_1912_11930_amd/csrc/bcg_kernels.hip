@@ -512,17 +512,41 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict
   reduce_entries<16, 64>(part, out, width, W, 0, nwg, blockIdx.x, sh);
 }
 
-// First stage for many partial rows: block (b, q) sums its share of the rows
-// for 16 entries into row q of `out` (kRedSplits rows of stride W), in the
-// same fixed order as k_reduce; a second pass then sums the kRedSplits rows.
-__global__ __launch_bounds__(kRedThreads) void k_reduce_rows(const double* __restrict__ part, double* __restrict__ out,
-                                                             int width, int W, int rows, const DevState* st) {
+// First stage for many partial rows: block (b, q) sums split q of the rows
+// (rows r0..r1-1) for 64 consecutive entries into row q of `out` (kRedSplits
+// rows of stride W); a second pass then sums the kRedSplits rows. Each wave
+// reads 512 contiguous bytes of a row per load, and a thread keeps 8 loads in
+// flight; thread slot s sums rows r0 + s, r0 + s + 4, ... in that order, and
+// the four slots are added in a fixed order, so the sums are reproducible.
+constexpr int kRowsEPB = 64, kRowsSlots = 4, kRowsBatch = 8;
+constexpr int kRowsThreads = kRowsEPB * kRowsSlots;
+__global__ __launch_bounds__(kRowsThreads) void k_reduce_rows(const double* __restrict__ part,
+                                                              double* __restrict__ out, int width, int W, int rows,
+                                                              const DevState* st) {
   if (stopped(st)) return;
-  __shared__ double sh[64][16];
+  __shared__ double sh[kRowsSlots][kRowsEPB];
   const int q = blockIdx.y;
   const int r0 = static_cast<int>(static_cast<int64_t>(rows) * q / kRedSplits);
   const int r1 = static_cast<int>(static_cast<int64_t>(rows) * (q + 1) / kRedSplits);
-  reduce_entries<16, 64>(part, out + (int64_t)q * W, width, W, r0, r1, blockIdx.x, sh);
+  const int le = threadIdx.x % kRowsEPB, s = threadIdx.x / kRowsEPB;
+  const int e = blockIdx.x * kRowsEPB + le;
+  double c[4] = {0.0, 0.0, 0.0, 0.0};
+  if (e < width) {
+    const int64_t step = static_cast<int64_t>(W) * kRowsSlots;
+    const double* p = part + static_cast<int64_t>(r0 + s) * W + e;
+    int r = r0 + s;
+    for (; r + (kRowsBatch - 1) * kRowsSlots < r1; r += kRowsBatch * kRowsSlots, p += kRowsBatch * step) {
+      double v[kRowsBatch];
+#pragma unroll
+      for (int t = 0; t < kRowsBatch; ++t) v[t] = p[t * step];
+#pragma unroll
+      for (int t = 0; t < kRowsBatch; ++t) c[t & 3] += v[t];
+    }
+    for (; r < r1; r += kRowsSlots, p += step) c[0] += *p;
+  }
+  sh[s][le] = (c[0] + c[1]) + (c[2] + c[3]);
+  __syncthreads();
+  if (s == 0 && e < width) out[(int64_t)q * W + e] = (sh[0][le] + sh[1][le]) + (sh[2][le] + sh[3][le]);
 }
 
 // True in the one workgroup of the launch that finishes its share last; its
@@ -1671,8 +1695,8 @@ void launch_reduce(const Plan& pl, const double* part, double* out, int width, D
                    double* scratch) {
   if (rows < 0) rows = pl.nwg;
   if (rows > kRedSplitRows && scratch != nullptr) {
-    hipLaunchKernelGGL(k_reduce_rows, dim3((width + 15) / 16, kRedSplits), dim3(kRedThreads), 0, s, part, scratch,
-                       width, pl.W, rows, st);
+    hipLaunchKernelGGL(k_reduce_rows, dim3((width + kRowsEPB - 1) / kRowsEPB, kRedSplits), dim3(kRowsThreads), 0, s,
+                       part, scratch, width, pl.W, rows, st);
     part = scratch;
     rows = kRedSplits;
   }
@@ -1685,8 +1709,8 @@ void launch_reduce_lambda(const Plan& pl, const double* partA, int a_rows, doubl
                           int r_rows, double* alpha, double* rho, double* lam, float* lam32, double* ws, DevState* st,
                           hipStream_t s) {
   if (a_rows > kRedSplitRows && scratch != nullptr) {
-    hipLaunchKernelGGL(k_reduce_rows, dim3((pl.E + 15) / 16, kRedSplits), dim3(kRedThreads), 0, s, partA, scratch,
-                       pl.E, pl.W, a_rows, st);
+    hipLaunchKernelGGL(k_reduce_rows, dim3((pl.E + kRowsEPB - 1) / kRowsEPB, kRedSplits), dim3(kRowsThreads), 0, s,
+                       partA, scratch, pl.E, pl.W, a_rows, st);
     partA = scratch;
     a_rows = kRedSplits;
   }
