@@ -136,12 +136,12 @@ def _is_fp32_kernel(name: str) -> bool:
     return "_f32" in name or "<float" in name
 
 
-def traffic_from(directory: str, workload: str, variant: str) -> int:
-    """Write profiles/traffic.json from four rocprofv3 --pmc databases under
-    `directory`: copy_fetch, copy_write (bench.py --copy-calibration) and
-    fetch, write (the benchmark, both precisions). FETCH_SIZE / WRITE_SIZE are
-    KiB per dispatch; each is scaled so that the plain copy reads and writes
-    COPY_BYTES."""
+def traffic_from(directory: str, workload: str, variant: str, path: str | None = None) -> int:
+    """Write profiles/traffic.json (or `path`) from four rocprofv3 --pmc
+    databases under `directory`: copy_fetch, copy_write (bench.py
+    --copy-calibration) and fetch, write (the benchmark, both precisions).
+    FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled so that the
+    plain copy reads and writes COPY_BYTES."""
     import glob
 
     def db(sub):
@@ -155,7 +155,7 @@ def traffic_from(directory: str, workload: str, variant: str) -> int:
     f_write = (COPY_BYTES / 1024) / copy_kib("copy_write", "WRITE_SIZE")
     fetch = _pmc_means(db("fetch"), "FETCH_SIZE")
     write = _pmc_means(db("write"), "WRITE_SIZE")
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = path or os.path.join(ROOT, "profiles", "traffic.json")
     rec = json.load(open(path)) if os.path.exists(path) else {}
     for precision in ("fp64", "fp32"):
         want32 = precision != "fp64"
