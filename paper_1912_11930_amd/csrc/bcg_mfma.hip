@@ -1565,14 +1565,15 @@ void mfma_sp_grid(Plan& pl) {
     }
     pl.ugw[prec] = gw;
     // vector update passes beside the matrix-core sparse product where they
-    // measured faster on the 256^3, k = 128 Poisson workload: FP32 R update
-    // and X/P pass for p <= 8 (5.0 against 5.4 ms and 8.0 against 9.2 ms at
-    // p = 8; 4.9 / 5.4 and 7.2 / 8.5 ms at p = 1), the FP64 R update for
+    // measured faster on the 256^3, k = 128 Poisson workload: the FP32 X/P
+    // pass for p <= 16 (9.1 against 9.6 ms at p = 16, 8.0 against 9.2 ms at
+    // p = 8), the FP32 R update for p <= 8 (5.0 against 5.4 ms at p = 8; at
+    // p = 16 the vector one takes 7.6 against 5.3 ms), the FP64 R update for
     // p <= 16 (9.5 against 10.4 ms at p = 16); k = 16 is faster on the matrix
     // cores throughout. BCG_UPDATE_VEC32 / BCG_UPDATE_VEC64 = 0..3 override
     // (bit 0: R update, bit 1: X/P pass).
     int vec = 0;
-    if (pl.fast && pl.k == 128) vec = prec ? (pl.p <= 8 ? 3 : 0) : 1;
+    if (pl.fast && pl.k == 128) vec = prec ? (pl.p <= 8 ? 3 : 2) : 1;
     if (const char* e = std::getenv(prec ? "BCG_UPDATE_VEC32" : "BCG_UPDATE_VEC64")) {
       const int v = std::atoi(e);
       if (v >= 0 && v <= 3) vec = pl.fast ? v : 0;
