@@ -56,6 +56,13 @@ def algorithmic_bytes(cls: str, n: int, nnz: int, k: int, precision: str) -> flo
     raise ValueError(cls)
 
 
+def solve_bytes(kernels: dict, n: int, nnz: int, k: int, precision: str) -> float:
+    """Algorithmic bytes of one solve's row passes: launches per class (of a
+    profiled solve) times the class's bytes per launch."""
+    return sum(algorithmic_bytes(c, n, nnz, k, precision) * kernels[c]["launches"]
+               for c in ("spmm", "update_r", "update_xp") if c in kernels)
+
+
 # sources that determine the HBM traffic of the row kernels: the kernels,
 # their launch plan and the stencil row order
 TRAFFIC_SOURCES = ("bcg_mfma.hip", "bcg_fast.hip", "bcg_internal.h", "bcg_stencil.hip")
@@ -444,6 +451,8 @@ def main() -> int:
                      "launches": head["launches"]},
         "kernels": head["kernels"],
         "kernels_total_ms": head["kernels_total_ms"],
+        # the row passes' algorithmic bytes of one solve over the timed solve time
+        "solve_GBps": solve_bytes(head["kernels"], n, nnz, k, args.precision) / (ms_per_step * 1e-3) / 1e9,
         "cpu_baseline": None,
     }
     if not args.no_compare:

@@ -25,6 +25,16 @@ def test_algorithmic_bytes():
         bench.algorithmic_bytes("reduce", n, z, k, "fp64")
 
 
+def test_solve_bytes():
+    n, z, k = 1000, 7000, 16
+    kernels = {"spmm": {"launches": 10}, "update_r": {"launches": 10}, "update_xp": {"launches": 11},
+               "small": {"launches": 20}}
+    want = (10 * bench.algorithmic_bytes("spmm", n, z, k, "fp64") + 10 * bench.algorithmic_bytes("update_r", n, z, k, "fp64")
+            + 11 * bench.algorithmic_bytes("update_xp", n, z, k, "fp64"))
+    assert bench.solve_bytes(kernels, n, z, k, "fp64") == want
+    assert bench.solve_bytes({}, n, z, k, "fp64") == 0
+
+
 def _db(path, rows):
     """A counters_collection table as rocprofv3 writes it (the columns read)."""
     os.makedirs(os.path.dirname(path), exist_ok=True)
